@@ -1,0 +1,3 @@
+"""FP64 CPU oracle (test infrastructure only; see excursion_set.py)."""
+from .excursion_set import *  # noqa: F401,F403
+from .excursion_set import Physics, Evaluation  # noqa: F401
