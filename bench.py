@@ -1,0 +1,179 @@
+"""Benchmark: walker likelihood evaluations per second at 256^3 x 3 redshifts.
+
+One step = the whole path over one batch: for each of the three boxes
+(256^3, 250 Mpc, z = 8, 9, 10) the forward FFT and every sharp-k smoothed box
+of the shared radius ladder, then for all 64 walkers the ionisation field,
+dT_b and binned P(k) on all three boxes.  value = walkers / step time.
+
+Also reported: the steady-state rate with the smoothed boxes resident (the MCMC
+loop), the plain per-walker form (recomputes the forward FFT and all smoothed
+boxes of the walker's own radii per evaluation), Gcell-R/s, the roofline of the
+dominant kernel (HIP events on the library stream inside the timed steps,
+algorithmic bytes), and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched-256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-walkers", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by walkers and "
+              "boxes across GPUs, which this build does not run", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1501_06576_amd as xs
+
+    if not os.path.exists(xs.LIB_PATH):
+        from paper_1501_06576_amd import build
+        build.build()
+    wl = synth.WORKLOADS[args.workload]
+    amp = synth.reference_amplitude()
+    log(f"workload {wl.name}: generating {len(wl.boxes)} boxes")
+    boxes = synth.workload_boxes(wl, amp)
+    walkers = synth.workload_walkers(wl)
+    nw = len(walkers)
+    ctx = xs.Context(0, phys=xs.physics(pk_amp=amp))
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    group = min(nw, 64)
+    ctx.prepare(wl.storage, max_walkers=group, max_plain_radii=40)
+    nbmax = max(s.n_bins for s in wl.boxes)
+    pk = torch.empty((nw, len(hs), nbmax), dtype=torch.float64, device="cuda")
+    xhi = torch.empty((nw, len(hs)), dtype=torch.float64, device="cuda")
+
+    def step():
+        for h in hs:
+            ctx.resmooth(h)
+        ctx.eval_batch(hs, walkers, pk, xhi)
+
+    def steady():
+        ctx.eval_batch(hs, walkers, pk, xhi)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("timing full steps")
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = nw / (ms_step * 1e-3)
+
+    # steady state: smoothed boxes resident, only the per-walker work
+    log("timing steady state")
+    for _ in range(2):
+        steady()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        steady()
+    torch.cuda.synchronize()
+    ms_steady = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # ionisation work: sum over walkers and boxes of N^3 x (radii the walker filters at)
+    cellR = 0.0
+    for h, s in zip(hs, wl.boxes):
+        shared = np.array(ctx.radii(h))
+        for w in walkers:
+            cellR += float(s.n) ** 3 * (np.count_nonzero(shared[:-1] <= w[1]) + 1)
+
+    # plain per-walker GPU form
+    log("timing plain per-walker form")
+    pw = walkers[: args.plain_walkers]
+    for h in hs:
+        ctx.eval(h, pw[0], fields=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in pw:
+        for h in hs:
+            ctx.eval(h, w, fields=False)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3 / len(pw)
+
+    # roofline of the dominant kernel class over the timed steps
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    bytes_launch = d["bytes"] / max(d["launches"], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
+                   "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items() if v["launches"]}
+
+    result = {
+        "metric": "walker likelihood evals/sec at 256^3 x 3 z; ionization Gcell-R/s; %HBM peak",
+        "value": round(value, 2),
+        "unit": "walker-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {len(hs)} boxes {wl.boxes[0].n}^3 / {wl.boxes[0].box_mpc} Mpc at z="
+                               + ",".join(str(s.z) for s in wl.boxes) + f", {nw} walkers, {wl.storage} smoothed boxes",
+                   "walkers": nw, "boxes": len(hs), "grid": wl.boxes[0].n, "parallelism": "single GPU"},
+        "gcell_r_per_s": round(cellR / (ms_step * 1e-3) / 1e9, 2),
+        "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
+                         "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2)},
+        "plain_per_walker": {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
+        "kernels": kernels,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_launch},
+    }
+
+    if not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle on one walker x one box")
+        import oracle
+        phys = oracle.Physics(pk_amp=amp)
+        s = wl.boxes[1]
+        w = walkers[0]
+        radii = oracle.walker_radii(ctx.radii(hs[1]), w[1])
+        t0 = time.perf_counter()
+        oracle.evaluate(boxes[1], s.box_mpc, s.z, w, radii, s.n_bins, phys)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(1.0 / (dt * len(hs)), 5), "unit": "walker-evals/s", "cores":
+                                  oracle.FFT_WORKERS, "kind": "oracle",
+                                  "sample": f"1 walker x 1 box ({s.n}^3, z={s.z}, {len(radii)} radii) in {dt:.2f} s; "
+                                            f"a walker eval is {len(hs)} boxes"}
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,264 @@
+/*
+ * xs21 -- excursion-set ionisation, 21 cm brightness temperature and binned
+ * power spectrum on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the likelihood core of 21CMMC (Greig & Mesinger 2015): for a
+ * fixed evolved density box and one astrophysical parameter set
+ * (zeta, R_mfp, T_vir) it computes
+ *
+ *   1. delta_R: the box smoothed with a sharp-k top hat for radii stepping down
+ *      from the largest filter scale to the cell size (Section 2.1);
+ *   2. the ionisation field: a cell is fully ionised when
+ *      zeta * f_coll(delta_R) >= 1 at any radius (eq. 1), with
+ *      f_coll = erfc((delta_c - delta_R) / sqrt(2 (sigma^2(M_min) - sigma^2(R)))),
+ *      otherwise it keeps the partial ionised fraction zeta * f_coll at the
+ *      cell radius (Section 2.1), with M_min from T_vir (eq. 3);
+ *   3. the brightness temperature dT_b = tb0 x_HI (1 + delta) sqrt((1+z)/10) mK
+ *      (eq. 4 with T_S >> T_gamma and without the velocity-gradient factor);
+ *   4. its spherically averaged power spectrum in logarithmic k bins
+ *      (Section 2.2).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Boxes are N^3 arrays in C order (last axis contiguous), N a power of two in
+ * [8, 512].  Lengths are comoving Mpc, masses Msun, temperatures K, dT_b mK,
+ * P(k) mK^2 Mpc^3 (per mode |X|^2 L^3 / N^6 with X the unnormalised DFT).
+ * k bins: edges e_b = k_f (N/2)^(b/n_bins), b = 0..n_bins, on [k_f, k_Nyquist];
+ * DC and modes with |n| > N/2 are dropped; the top edge is closed.
+ * Filter: W_R(k) = 1 for |k| <= k_c = (9 pi / 2)^(1/3) / R (volume matching).
+ * Radii: the shared ladder of a box is R_i = ladder_top / radius_step^i while
+ * R_i > L/N, then L/N.  A walker of mean free path R_mfp uses the radii of the
+ * ladder with R <= R_mfp (and always the cell radius).
+ *
+ * Ownership.  The caller owns every buffer.  All device memory the library
+ * uses is one workspace the caller allocates (e.g. a torch tensor) and passes
+ * to xs21_prepare; the library keeps only host-side tables and that pointer.
+ * Host input boxes are copied by xs21_add_box and may be freed afterwards;
+ * device input boxes are copied by xs21_prepare and may be freed after it.
+ *
+ * Errors.  Every call returns xs21_status; nothing else crosses the ABI.  On
+ * error the outputs are unspecified and xs21_last_error() describes the
+ * cause (thread-local, valid until the next call on the same thread).  After
+ * XS21_EINVAL, XS21_ENOMEM or XS21_EUNSUPPORTED the context stays usable.
+ * After XS21_EDEVICE the context is poisoned and every later call on it
+ * returns XS21_ESTATE.
+ *
+ * Threading.  A context belongs to one host thread and one HIP stream.
+ */
+#ifndef XS21_H
+#define XS21_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  XS21_OK = 0,
+  XS21_EINVAL = -1,       /* argument out of range, NaN, unknown handle       */
+  XS21_ENOMEM = -2,       /* workspace too small / host allocation failed     */
+  XS21_EDEVICE = -3,      /* a HIP call failed; the context is poisoned       */
+  XS21_EUNSUPPORTED = -4, /* valid request this build does not implement      */
+  XS21_ESTATE = -5        /* call out of order, or context poisoned           */
+} xs21_status;
+
+typedef enum { XS21_F32 = 0, XS21_F64 = 1, XS21_BF16 = 2 } xs21_dtype;
+
+/* Constants of the method.  xs21_physics_default() fills the values used
+ * throughout the paper (Section 1 cosmology) and the synthetic spectrum shape. */
+typedef struct {
+  double delta_c;     /* linear collapse threshold, 1.686                          */
+  double omega_m;     /* 0.27 (Section 1)                                          */
+  double omega_l;     /* 0.73                                                      */
+  double h;           /* 0.7                                                       */
+  double tb0_mK;      /* 27 mK prefactor of eq. (4)                                */
+  double pk_amp;      /* A of P(k) = A k (1 + (k/k0)^2)^-2 at z_ref, Mpc^4          */
+  double pk_k0;       /* k0, Mpc^-1 (0.05)                                         */
+  double z_ref;       /* redshift of pk_amp; D(z) = (1+z_ref)/(1+z) (9)            */
+  double radius_step; /* ratio of consecutive radii (1.1)                          */
+  double ladder_top;  /* top radius of the shared ladder, Mpc (20)                 */
+  double mu;          /* mean molecular weight in eq. (3) (0.6)                    */
+  int32_t mmin_form;  /* 0: M_min = 1e8 (T/1e4)^1.5 ((1+z)/10)^-1.5; 1: eq. (3)     */
+  int32_t reserved;
+} xs21_physics;
+
+/* One astrophysical parameter set (Section 2.1). */
+typedef struct {
+  double zeta;   /* ionising efficiency, > 0                */
+  double r_mfp;  /* mean free path / largest filter, Mpc > 0 */
+  double t_vir;  /* minimum virial temperature, K > 0       */
+} xs21_walker;
+
+typedef struct xs21_ctx xs21_ctx;
+typedef int32_t xs21_box;
+
+/* ---------------------------------------------------------------- basics */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* xs21_last_error(void);
+
+/* Fills *p with the default constants.  p must not be NULL. */
+xs21_status xs21_physics_default(xs21_physics* p);
+
+/* Creates a context bound to HIP device `hip_device` and stream `hip_stream`
+ * (a hipStream_t; NULL selects the default stream).  Constants are copied.
+ * EINVAL: bad constants; EDEVICE: the device cannot be selected. */
+xs21_status xs21_create(xs21_ctx** out, int hip_device, void* hip_stream,
+                        const xs21_physics* phys);
+
+/* Releases the host-side state of a context.  NULL is accepted. */
+xs21_status xs21_destroy(xs21_ctx* ctx);
+
+/* Blocks until all work queued by the context on its stream has finished. */
+xs21_status xs21_sync(xs21_ctx* ctx);
+
+/* ---------------------------------------------------------------- boxes */
+
+/* Registers a density box delta(x) of n^3 cells, side box_mpc, redshift z,
+ * with n_bins logarithmic power-spectrum bins.
+ * delta: n^3 values of `dtype` (XS21_F32 or XS21_F64) in C order, on the host
+ * (on_device = 0, copied now) or on the device (on_device = 1, copied by
+ * xs21_prepare).  The box dtype fixes the arithmetic of everything computed
+ * on it: F64 boxes run the whole path in double precision, F32 boxes in
+ * single precision with FP64 host planning and FP64 bin sums.
+ * Must be called before xs21_prepare.
+ * EINVAL: n not a power of two in [8, 512], box_mpc <= 0, z <= -1, n_bins
+ * outside [1, 64], non-finite values; ESTATE: after xs21_prepare. */
+xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_dtype dtype,
+                         int n, double box_mpc, double z, int n_bins, xs21_box* out);
+
+/* Shared radius ladder of a registered box (Section 2.1: decreasing radii
+ * from ladder_top down to the cell size L/n).  Writes up to `cap` radii, in
+ * decreasing order, to out (may be NULL) and their count to *n_radii. */
+xs21_status xs21_box_radii(xs21_ctx* ctx, xs21_box box, double* out, int cap, int* n_radii);
+
+/* k_b (count-weighted mean |k| per bin, Mpc^-1) and mode counts c_b of a box
+ * geometry; each array holds n_bins doubles. Either pointer may be NULL. */
+xs21_status xs21_box_bins(xs21_ctx* ctx, xs21_box box, double* k_mean, double* counts);
+
+/* ---------------------------------------------------------------- workspace */
+
+/* Bytes of device workspace needed to prepare every registered box with
+ * smoothed boxes stored as `storage` (F32 or BF16 for F32 boxes, F64 for F64
+ * boxes), evaluate up to `max_walkers` walkers per xs21_eval_batch launch
+ * group, and run plain evaluations with up to `max_plain_radii` radii. */
+xs21_status xs21_workspace_size(xs21_ctx* ctx, xs21_dtype storage, int max_walkers,
+                                int max_plain_radii, size_t* bytes);
+
+/* Computes, on the context stream, the forward FFT of every registered box
+ * and every smoothed box delta_R of its shared ladder, and keeps them
+ * resident in the workspace (the radius loop of Section 2.1 is independent of
+ * the walker, so it runs once per box).  `workspace` is device memory of at
+ * least xs21_workspace_size(...) bytes, 256-byte aligned, owned by the caller
+ * and left untouched by anyone else until the context is destroyed.
+ * ENOMEM: workspace too small; EINVAL: storage not allowed for a box dtype. */
+xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtype storage,
+                         int max_walkers, int max_plain_radii);
+
+/* Recomputes, on the context stream, the forward FFT and every smoothed box
+ * of `box` from its resident density (the same work xs21_prepare does for
+ * it).  With new_delta != NULL the resident density is first replaced by
+ * new_delta (DEVICE, n^3 values of the box dtype, copied).  Asynchronous.
+ * ESTATE: not prepared. */
+xs21_status xs21_resmooth(xs21_ctx* ctx, xs21_box box, const void* new_delta);
+
+/* ---------------------------------------------------------------- evaluation */
+
+/* Batched evaluation on the resident smoothed boxes: for each walker w and
+ * box b, the ionisation field (eq. 1 on the walker's suffix of the shared
+ * ladder; partial ionisation at the cell radius), dT_b (eq. 4) and its binned
+ * power spectrum.  Asynchronous on the context stream.
+ * Outputs are DEVICE arrays: pk[nw][nb][n_bins_max] (P_b, mK^2 Mpc^3; bins past
+ * a box's own n_bins are set to 0) and xhi_mean[nw][nb] (volume-weighted mean
+ * neutral fraction); n_bins_max is the largest n_bins of the listed boxes.
+ * Either output may be NULL.  Walkers are processed in groups of at most
+ * max_walkers.  All listed boxes must share the dtype of the first.
+ * EINVAL: bad walker values or box handles; ESTATE: not prepared. */
+xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb,
+                            const xs21_walker* walkers, int nw, double* pk, double* xhi_mean);
+
+/* Plain evaluation of one walker on one box: the literal per-walker method.
+ * The forward FFT and every smoothed box of the walker's own radius list are
+ * recomputed (radii given explicitly, decreasing, last = cell radius; NULL
+ * selects R_mfp / radius_step^i down to the cell size).  Synchronous.
+ * Outputs are HOST arrays and each may be NULL: x_hi and dtb hold n^3 values
+ * of the box dtype; pk, k_mean and counts hold n_bins doubles; xhi_mean one
+ * double.  ENOMEM: more radii than max_plain_radii. */
+xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
+                      const double* radii, int n_radii, void* x_hi, void* dtb,
+                      double* pk, double* k_mean, double* counts, double* xhi_mean);
+
+/* Batched-path fields of one walker on one box, from the resident smoothed
+ * boxes (same kernels as xs21_eval_batch).  x_hi and dtb are DEVICE arrays of
+ * n^3 values of the box dtype; either may be NULL.  Asynchronous. */
+xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
+                             void* x_hi, void* dtb);
+
+/* Copies smoothed box `index` of the shared ladder of `box` into `out` (DEVICE,
+ * n^3 values of the box dtype, converted from the storage type). Asynchronous. */
+xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out);
+
+/* Binned power spectrum (Section 2.2) of a caller-given real field on the
+ * geometry of `box`, through the same FFT and binning kernels as the
+ * evaluation.  field: DEVICE, n^3 values of the box dtype.  pk: HOST, n_bins
+ * doubles.  Synchronous. */
+xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk);
+
+/* ---------------------------------------------------------------- kernel timing */
+
+/* Kernel classes timed by xs21_profile_read. */
+typedef enum {
+  XS21_K_ROWS_R2C = 0,   /* x pass of a forward transform of a real box        */
+  XS21_K_ROWS_C2R = 1,   /* x pass of an inverse transform (writes delta_R)   */
+  XS21_K_AXIS_FWD = 2,   /* y or z pass of a forward transform                */
+  XS21_K_AXIS_INV = 3,   /* y or z pass of an inverse transform (z: + filter) */
+  XS21_K_AXIS_BINS = 4,  /* forward z pass fused with |X|^2 binning           */
+  XS21_K_ION = 5,        /* per-cell ionisation + dT_b + forward x pass        */
+  XS21_K_FINALIZE = 6,   /* FP64 reduction of bin and x_HI partial sums        */
+  XS21_K_OTHER = 7,      /* materialisation and casts                          */
+  XS21_K_COUNT = 8
+} xs21_kernel;
+
+/* enable != 0: from now on every kernel launch of the context is bracketed by
+ * HIP events on the context stream and its duration accumulated per class;
+ * totals are cleared.  enable == 0: stop recording. */
+xs21_status xs21_profile(xs21_ctx* ctx, int enable);
+
+/* Synchronises the context stream, then returns for kernel class `kind` the
+ * summed duration (ms), the number of launches, and the summed algorithmic
+ * bytes (the compulsory HBM reads + writes of each launch's inputs and
+ * outputs).  Any output pointer may be NULL. */
+xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes);
+
+/* ---------------------------------------------------------------- host planning */
+/* Pure host functions (no device, no context): the FP64 scalar planning the
+ * kernels consume, exposed so it can be checked on its own. */
+
+/* Radius ladder R_i = r_top / step^i while R_i > r_cell, then r_cell. */
+xs21_status xs21_plan_ladder(double r_top, double r_cell, double step, double* out, int cap,
+                             int* n_radii);
+
+/* sigma^2(R, z) of the sharp-k window on the linear spectrum of `phys`. */
+xs21_status xs21_plan_sigma2(const xs21_physics* phys, double radius, double z, double* out);
+
+/* Per-radius flag thresholds of one walker at redshift z over `radii`
+ * (decreasing, last = cell radius).  thr[j]: a cell is fully ionised at
+ * radius j when delta_R >= thr[j] (the exact rewrite of zeta f_coll >= 1 via
+ * the inverse of erfc); +inf where no cell can be (sigma^2(M_min) <=
+ * sigma^2(R_j) or zeta <= 1/2).  dsig2[j] = sigma^2(M_min) - sigma^2(R_j).
+ * *first: index of the first radius <= r_mfp.  *m_min: M_min in Msun.
+ * Any output pointer may be NULL. */
+xs21_status xs21_plan_walker(const xs21_physics* phys, double z, const double* radii,
+                             int n_radii, const xs21_walker* walker, double* thr,
+                             double* dsig2, int* first, double* m_min);
+
+/* Bin index of every integer |n|^2 in [0, 3 (n/2)^2] (-1 = dropped). out
+ * holds 3 (n/2)^2 + 1 entries. */
+xs21_status xs21_plan_bins(int n, int n_bins, int8_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XS21_H */

@@ -40,7 +40,15 @@ import scipy.fft
 import scipy.integrate
 import scipy.special
 
-FFT_WORKERS = os.cpu_count() or 1
+def _cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+FFT_WORKERS = _cores()  # threads the oracle's FFTs use (at most 16)
 
 
 # ---------------------------------------------------------------------------

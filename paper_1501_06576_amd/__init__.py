@@ -1,0 +1,318 @@
+"""xs21: excursion-set ionisation -> 21 cm brightness -> P(k) on MI355X (gfx950).
+
+Thin ctypes binding of libxs21.so.  It only marshals arguments: every step of
+the path runs in the library's HIP kernels.  PyTorch provides device memory
+(the workspace and output tensors) and the HIP stream.  There is no fallback:
+if the built library is missing, importing the binding raises.
+
+Paper: Greig & Mesinger 2015, 21CMMC (Section 2.1 ionisation field, eq. 1 and
+eq. 3; Section 2.2 brightness temperature eq. 4 and the power spectrum).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxs21.so")
+
+F32, F64, BF16 = 0, 1, 2
+KERNELS = ("rows_r2c", "rows_c2r", "axis_fwd", "axis_inv", "axis_bins", "ion", "finalize", "other")
+_DTYPES = {"f32": F32, "f64": F64, "bf16": BF16}
+
+
+class Xs21Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"xs21 status {status}: {msg}")
+        self.status = status
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [("delta_c", ctypes.c_double), ("omega_m", ctypes.c_double), ("omega_l", ctypes.c_double),
+                ("h", ctypes.c_double), ("tb0_mK", ctypes.c_double), ("pk_amp", ctypes.c_double),
+                ("pk_k0", ctypes.c_double), ("z_ref", ctypes.c_double), ("radius_step", ctypes.c_double),
+                ("ladder_top", ctypes.c_double), ("mu", ctypes.c_double), ("mmin_form", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Walker(ctypes.Structure):
+    _fields_ = [("zeta", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_vir", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+_SIGNATURES = {
+    "xs21_last_error": (ctypes.c_char_p, []),
+    "xs21_physics_default": (_I, [ctypes.POINTER(Physics)]),
+    "xs21_create": (_I, [ctypes.POINTER(_P), _I, _P, ctypes.POINTER(Physics)]),
+    "xs21_destroy": (_I, [_P]),
+    "xs21_sync": (_I, [_P]),
+    "xs21_add_box": (_I, [_P, _P, _I, _I, _I, _D, _D, _I, ctypes.POINTER(ctypes.c_int32)]),
+    "xs21_box_radii": (_I, [_P, _I, _DP, _I, _IP]),
+    "xs21_box_bins": (_I, [_P, _I, _DP, _DP]),
+    "xs21_workspace_size": (_I, [_P, _I, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
+    "xs21_prepare": (_I, [_P, _P, ctypes.c_size_t, _I, _I, _I]),
+    "xs21_eval_batch": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker), _I, _P, _P]),
+    "xs21_eval": (_I, [_P, _I, ctypes.POINTER(Walker), _DP, _I, _P, _P, _DP, _DP, _DP, _DP]),
+    "xs21_materialize": (_I, [_P, _I, ctypes.POINTER(Walker), _P, _P]),
+    "xs21_smoothed": (_I, [_P, _I, _I, _P]),
+    "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
+    "xs21_resmooth": (_I, [_P, _I, _P]),
+    "xs21_profile": (_I, [_P, _I]),
+    "xs21_profile_read": (_I, [_P, _I, _DP, ctypes.POINTER(ctypes.c_longlong), _DP]),
+    "xs21_plan_ladder": (_I, [_D, _D, _D, _DP, _I, _IP]),
+    "xs21_plan_sigma2": (_I, [ctypes.POINTER(Physics), _D, _D, _DP]),
+    "xs21_plan_walker": (_I, [ctypes.POINTER(Physics), _D, _DP, _I, ctypes.POINTER(Walker), _DP, _DP, _IP, _DP]),
+    "xs21_plan_bins": (_I, [_I, _I, ctypes.POINTER(ctypes.c_int8)]),
+}
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Loads libxs21.so (built by paper_1501_06576_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_06576_amd.build` "
+                              "(hipcc, gfx950); there is no fallback implementation")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise Xs21Error(status, library().xs21_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def physics(**overrides) -> Physics:
+    p = Physics()
+    _check(library().xs21_physics_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+# ------------------------------------------------------------------ host planning
+
+def plan_ladder(r_top: float, r_cell: float, step: float) -> List[float]:
+    n = ctypes.c_int()
+    _check(library().xs21_plan_ladder(r_top, r_cell, step, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value)
+    _check(library().xs21_plan_ladder(r_top, r_cell, step, _dptr(out), n.value, ctypes.byref(n)))
+    return out.tolist()
+
+
+def plan_sigma2(phys: Physics, radius: float, z: float) -> float:
+    v = ctypes.c_double()
+    _check(library().xs21_plan_sigma2(ctypes.byref(phys), radius, z, ctypes.byref(v)))
+    return v.value
+
+
+def plan_walker(phys: Physics, z: float, radii: Sequence[float], walker: Sequence[float]):
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    thr = np.zeros(len(r))
+    ds = np.zeros(len(r))
+    first = ctypes.c_int()
+    mmin = ctypes.c_double()
+    w = Walker(*map(float, walker))
+    _check(library().xs21_plan_walker(ctypes.byref(phys), z, _dptr(r), len(r), ctypes.byref(w), _dptr(thr),
+                                      _dptr(ds), ctypes.byref(first), ctypes.byref(mmin)))
+    return {"thr": thr, "dsig2": ds, "first": first.value, "m_min": mmin.value}
+
+
+def plan_bins(n: int, n_bins: int) -> np.ndarray:
+    out = np.zeros(3 * (n // 2) ** 2 + 1, dtype=np.int8)
+    _check(library().xs21_plan_bins(n, n_bins, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+    return out
+
+
+# ------------------------------------------------------------------ device context
+
+def _walkers_array(walkers) -> Tuple[ctypes.Array, int]:
+    w = np.ascontiguousarray(np.asarray(walkers, dtype=np.float64).reshape(-1, 3))
+    arr = (Walker * len(w))()
+    ctypes.memmove(arr, w.ctypes.data, w.nbytes)
+    return arr, len(w)
+
+
+class Context:
+    """One xs21 context on one GPU and one HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None, phys: Optional[Physics] = None):
+        import torch  # device memory and streams only
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.phys = phys if phys is not None else physics()
+        self._ctx = ctypes.c_void_p()
+        _check(library().xs21_create(ctypes.byref(self._ctx), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(self.phys)))
+        self.boxes: List[dict] = []
+        self.workspace = None
+        self._keep = []
+
+    def close(self):
+        if self._ctx:
+            library().xs21_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_box(self, delta, box_mpc: float, z: float, n_bins: int) -> int:
+        """Registers a density box (numpy array on the host or torch tensor on this GPU)."""
+        torch = self.torch
+        h = ctypes.c_int32()
+        if isinstance(delta, torch.Tensor) and delta.is_cuda:
+            t = delta.contiguous()
+            dt = F64 if t.dtype == torch.float64 else F32
+            self._keep.append(t)  # must outlive prepare
+            n = t.shape[0]
+            _check(library().xs21_add_box(self._ctx, ctypes.c_void_p(t.data_ptr()), 1, dt, n, box_mpc, z, n_bins,
+                                          ctypes.byref(h)))
+        else:
+            a = np.ascontiguousarray(delta)
+            if a.dtype not in (np.float32, np.float64):
+                raise TypeError("density box must be float32 or float64")
+            dt = F64 if a.dtype == np.float64 else F32
+            n = a.shape[0]
+            _check(library().xs21_add_box(self._ctx, a.ctypes.data_as(ctypes.c_void_p), 0, dt, n, box_mpc, z,
+                                          n_bins, ctypes.byref(h)))
+        self.boxes.append({"n": n, "box": box_mpc, "z": z, "n_bins": n_bins, "dtype": dt})
+        return h.value
+
+    def radii(self, box: int) -> List[float]:
+        n = ctypes.c_int()
+        _check(library().xs21_box_radii(self._ctx, box, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value)
+        _check(library().xs21_box_radii(self._ctx, box, _dptr(out), n.value, ctypes.byref(n)))
+        return out.tolist()
+
+    def bins(self, box: int):
+        nb = self.boxes[box]["n_bins"]
+        km = np.zeros(nb)
+        cn = np.zeros(nb)
+        _check(library().xs21_box_bins(self._ctx, box, _dptr(km), _dptr(cn)))
+        return km, cn
+
+    def workspace_size(self, storage="f32", max_walkers=64, max_plain_radii=40) -> int:
+        v = ctypes.c_size_t()
+        _check(library().xs21_workspace_size(self._ctx, _DTYPES[storage], max_walkers, max_plain_radii,
+                                             ctypes.byref(v)))
+        return v.value
+
+    def prepare(self, storage="f32", max_walkers=64, max_plain_radii=40):
+        """Allocates the workspace (one torch uint8 tensor) and builds the resident smoothed boxes."""
+        torch = self.torch
+        nbytes = self.workspace_size(storage, max_walkers, max_plain_radii)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        _check(library().xs21_prepare(self._ctx, ctypes.c_void_p(ws.data_ptr() + off), nbytes, _DTYPES[storage],
+                                      max_walkers, max_plain_radii))
+        self._keep.clear()
+
+    def eval_batch(self, boxes: Sequence[int], walkers, pk=None, xhi=None):
+        """Batched evaluation; returns device tensors pk [nw, nb, nbmax] and xhi [nw, nb] (float64)."""
+        torch = self.torch
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        warr, nw = _walkers_array(walkers)
+        nbmax = max(self.boxes[b]["n_bins"] for b in boxes)
+        if pk is None:
+            pk = torch.empty((nw, len(boxes), nbmax), dtype=torch.float64, device=self.device)
+        if xhi is None:
+            xhi = torch.empty((nw, len(boxes)), dtype=torch.float64, device=self.device)
+        _check(library().xs21_eval_batch(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()),
+                                         ctypes.c_void_p(xhi.data_ptr())))
+        return pk, xhi
+
+    def eval(self, box: int, walker, radii=None, fields=True) -> dict:
+        """Plain per-walker evaluation (recomputes every smoothed box); host outputs."""
+        b = self.boxes[box]
+        n, nb = b["n"], b["n_bins"]
+        dt = np.float64 if b["dtype"] == F64 else np.float32
+        w = Walker(*map(float, walker))
+        r = None if radii is None else np.ascontiguousarray(radii, dtype=np.float64)
+        x_hi = np.empty((n, n, n), dtype=dt) if fields else None
+        dtb = np.empty((n, n, n), dtype=dt) if fields else None
+        pk = np.zeros(nb)
+        km = np.zeros(nb)
+        cn = np.zeros(nb)
+        xm = ctypes.c_double()
+        _check(library().xs21_eval(self._ctx, box, ctypes.byref(w), None if r is None else _dptr(r),
+                                   0 if r is None else len(r),
+                                   None if x_hi is None else x_hi.ctypes.data_as(ctypes.c_void_p),
+                                   None if dtb is None else dtb.ctypes.data_as(ctypes.c_void_p),
+                                   _dptr(pk), _dptr(km), _dptr(cn), ctypes.byref(xm)))
+        return {"x_hi": x_hi, "dtb": dtb, "pk": pk, "k_mean": km, "counts": cn, "xhi_mean": xm.value}
+
+    def materialize(self, box: int, walker):
+        """x_HI and dT_b of one walker from the resident smoothed boxes (device tensors)."""
+        torch = self.torch
+        b = self.boxes[box]
+        n = b["n"]
+        td = torch.float64 if b["dtype"] == F64 else torch.float32
+        x = torch.empty((n, n, n), dtype=td, device=self.device)
+        d = torch.empty((n, n, n), dtype=td, device=self.device)
+        w = Walker(*map(float, walker))
+        _check(library().xs21_materialize(self._ctx, box, ctypes.byref(w), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(d.data_ptr())))
+        return x, d
+
+    def smoothed(self, box: int, index: int):
+        torch = self.torch
+        b = self.boxes[box]
+        n = b["n"]
+        td = torch.float64 if b["dtype"] == F64 else torch.float32
+        out = torch.empty((n, n, n), dtype=td, device=self.device)
+        _check(library().xs21_smoothed(self._ctx, box, index, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def power_spectrum(self, box: int, field) -> np.ndarray:
+        b = self.boxes[box]
+        pk = np.zeros(b["n_bins"])
+        f = field.contiguous()
+        _check(library().xs21_power_spectrum(self._ctx, box, ctypes.c_void_p(f.data_ptr()), _dptr(pk)))
+        return pk
+
+    def resmooth(self, box: int, new_delta=None):
+        """Recomputes the forward FFT and the smoothed boxes of `box` (optionally from new device data)."""
+        ptr = None if new_delta is None else ctypes.c_void_p(new_delta.data_ptr())
+        _check(library().xs21_resmooth(self._ctx, box, ptr))
+
+    def profile(self, enable: bool = True):
+        _check(library().xs21_profile(self._ctx, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Per kernel class: total ms, launches and algorithmic bytes since profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            by = ctypes.c_double()
+            _check(library().xs21_profile_read(self._ctx, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": by.value}
+        return out
+
+    def sync(self):
+        _check(library().xs21_sync(self._ctx))

@@ -1,0 +1,844 @@
+// C-ABI of the xs21 library: context, boxes, workspace layout, prepare and
+// evaluation drivers.  All device memory is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xs21.h"
+#include "common.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace {
+
+using xs21::cplx;
+using xs21::WalkerConst;
+
+constexpr int kNtab = 512;       // twiddle table length (largest transform)
+constexpr size_t kAlign = 256;
+
+thread_local std::string g_error;
+
+xs21_status fail(xs21_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t real_size(int dtype) { return dtype == xs21::kF64 ? 8 : 4; }
+size_t store_size(int storage) { return storage == xs21::kF64 ? 8 : (storage == xs21::kF32 ? 4 : 2); }
+
+struct BoxRec {
+  int n = 0;
+  double box = 0, z = 0;
+  int nbins = 0;
+  int dtype = 0;
+  std::vector<unsigned char> host;  // host copy until prepare
+  const void* dev_src = nullptr;
+  std::vector<double> radii;
+  std::vector<long> n2max;
+  std::vector<int8_t> bintab;
+  std::vector<double> counts, kmean;
+  int storage = 0;
+  // workspace offsets
+  size_t off_bintab = 0, off_counts = 0, off_delta = 0, off_dR = 0;
+
+  size_t cells() const { return static_cast<size_t>(n) * n * n; }
+  size_t half() const { return static_cast<size_t>(n / 2 + 1); }
+  size_t spec_bytes() const { return static_cast<size_t>(n) * n * half() * 2 * real_size(dtype); }
+  int nr() const { return static_cast<int>(radii.size()); }
+  size_t wc_size() const { return dtype == xs21::kF64 ? sizeof(WalkerConst<double>) : sizeof(WalkerConst<float>); }
+  size_t table_bytes(int walkers) const {
+    return align_up(walkers * wc_size()) + align_up(static_cast<size_t>(walkers) * nr() * real_size(dtype));
+  }
+};
+
+struct Layout {
+  size_t tw32 = 0, tw64 = 0;
+  size_t tables = 0, tables_bytes = 0;     // batched walker tables (all boxes)
+  size_t one_table = 0, one_table_bytes = 0;  // single-walker table
+  size_t outs = 0;                          // small device outputs (plain / debug)
+  size_t scratch = 0, scratch_bytes = 0;    // union of prepare / eval / plain scratch
+  size_t total = 0;
+};
+
+}  // namespace
+
+struct xs21_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  xs21_physics phys{};
+  std::vector<BoxRec> boxes;
+  bool prepared = false;
+  bool poisoned = false;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int storage = 0;
+  int max_walkers = 0;
+  int max_plain = 0;
+  int group = 0;
+  Layout lay;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  // kernel timing
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  double tot_ms[XS21_K_COUNT] = {};
+  long long launches[XS21_K_COUNT] = {};
+  double tot_bytes[XS21_K_COUNT] = {};
+};
+
+namespace {
+
+xs21_status hip_fail(xs21_ctx* c, hipError_t e, const char* what) {
+  if (c) c->poisoned = true;
+  return fail(XS21_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHECK(ctx, call)                                  \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+xs21_status check_ctx(xs21_ctx* c) {
+  if (!c) return fail(XS21_EINVAL, "null context");
+  if (c->poisoned) return fail(XS21_ESTATE, "context poisoned by an earlier device error");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  return XS21_OK;
+}
+
+xs21_status check_box(xs21_ctx* c, xs21_box b) {
+  if (b < 0 || b >= static_cast<int>(c->boxes.size())) return fail(XS21_EINVAL, "unknown box handle %d", b);
+  return XS21_OK;
+}
+
+hipEvent_t pooled_event(xs21_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launches through `f`; when timing is on, brackets it with events on the
+// context stream and remembers the pair with the launch's algorithmic bytes.
+template <typename F>
+hipError_t timed(xs21_ctx* c, int kind, double bytes, F&& f) {
+  if (!c->prof) return f();
+  hipEvent_t a = pooled_event(c), b = pooled_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, c->stream);
+  if (e != hipSuccess) return e;
+  c->pending.push_back({kind, a, b, bytes});
+  return hipSuccess;
+}
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+int box_storage(const BoxRec& b, int storage) { return b.dtype == xs21::kF64 ? xs21::kF64 : storage; }
+
+// Scratch needed by each phase, per box; the scratch region is their maximum.
+size_t prepare_scratch(const BoxRec& b) { return 2 * align_up(b.spec_bytes()); }
+
+size_t eval_scratch(const BoxRec& b, int group) {
+  const long tiles = xs21::axis_tiles(b.n, static_cast<long>(b.n) * b.half());
+  return align_up(group * b.spec_bytes()) + align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
+         align_up(static_cast<size_t>(group) * xs21::ion_grid(b.n) * 8);
+}
+
+size_t plain_scratch(const BoxRec& b, int max_plain) {
+  return 2 * align_up(b.spec_bytes()) + align_up(static_cast<size_t>(max_plain) * b.cells() * real_size(b.dtype)) +
+         eval_scratch(b, 1);
+}
+
+Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_plain, int group,
+                      std::vector<BoxRec>& boxes) {
+  Layout L;
+  size_t off = 0;
+  L.tw32 = off;
+  off += align_up(kNtab * 8);
+  L.tw64 = off;
+  off += align_up(kNtab * 16);
+  size_t tables = 0, one = 0, scratch = 0;
+  for (auto& b : boxes) {
+    b.storage = box_storage(b, storage);
+    b.off_bintab = off;
+    off += align_up(b.bintab.size());
+    b.off_counts = off;
+    off += align_up(b.nbins * 8);
+    b.off_delta = off;
+    off += align_up(b.cells() * real_size(b.dtype));
+    b.off_dR = off;
+    off += align_up(static_cast<size_t>(b.nr()) * b.cells() * store_size(b.storage));
+    tables += b.table_bytes(max_walkers);
+    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(std::max(max_plain, b.nr()) * 8));
+    scratch = std::max({scratch, prepare_scratch(b), eval_scratch(b, group), plain_scratch(b, max_plain)});
+  }
+  (void)c;
+  L.tables = off;
+  L.tables_bytes = tables;
+  off += align_up(tables);
+  L.one_table = off;
+  L.one_table_bytes = one;
+  off += align_up(one);
+  L.outs = off;
+  off += align_up(8 * 256);
+  L.scratch = off;
+  L.scratch_bytes = scratch;
+  off += align_up(scratch);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned char* wc_dst, T* thr_dst,
+                       double zeta) {
+  WalkerConst<T> c;
+  c.zeta = static_cast<T>(zeta);
+  c.a_cell = static_cast<T>(wp.a_cell);
+  c.first = plain ? 0 : wp.first;
+  c.partial = wp.partial ? 1 : 0;
+  std::memcpy(wc_dst, &c, sizeof c);
+  for (size_t j = 0; j < wp.thr.size(); ++j) thr_dst[j] = static_cast<T>(wp.thr[j]);
+}
+
+// Writes the constants + thresholds of `walkers` for box b into host memory
+// laid out as [WalkerConst x count][thr x count x nr].
+void build_tables(const xs21_physics& p, const BoxRec& b, const xs21_walker* w, int count, bool plain,
+                  const std::vector<double>& radii, unsigned char* dst, int capacity) {
+  const size_t wcs = b.wc_size();
+  unsigned char* thr_base = dst + align_up(capacity * wcs);
+  const int nr = static_cast<int>(radii.size());
+  for (int i = 0; i < count; ++i) {
+    const auto wp = xs21::plan::walker(p, b.z, radii.data(), nr, w[i]);
+    if (b.dtype == xs21::kF64)
+      fill_walker_table<double>(wp, plain, dst + i * wcs, reinterpret_cast<double*>(thr_base) + static_cast<size_t>(i) * nr,
+                                w[i].zeta);
+    else
+      fill_walker_table<float>(wp, plain, dst + i * wcs, reinterpret_cast<float*>(thr_base) + static_cast<size_t>(i) * nr,
+                               w[i].zeta);
+  }
+}
+
+const void* tw_ptr(const xs21_ctx* c, int dtype) {
+  return c->ws + (dtype == xs21::kF64 ? c->lay.tw64 : c->lay.tw32);
+}
+
+// Forward 3D real-to-half-complex transform of a real box (in place in `spec`).
+hipError_t forward3d(xs21_ctx* c, const BoxRec& b, const void* real_in, void* spec) {
+  const long n = b.n, h = static_cast<long>(b.half());
+  const double rs = static_cast<double>(real_size(b.dtype));
+  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  const void* tw = tw_ptr(c, b.dtype);
+  hipError_t e = timed(c, XS21_K_ROWS_R2C, cells * rs + modes * 2 * rs, [&] {
+    return xs21::launch_rows_r2c(b.dtype, b.n, real_in, spec, n * n, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, n, h, -1, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  return timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, 1, n * h, -1, tw, kNtab, c->stream);
+  });
+}
+
+// delta_R = IDFT(mask_R * hat) / N^3 stored as `storage`.
+hipError_t smooth3d(xs21_ctx* c, const BoxRec& b, const void* hat, void* tmp, long n2max, int storage, void* out) {
+  const long n = b.n, h = static_cast<long>(b.half());
+  const double rs = static_cast<double>(real_size(b.dtype));
+  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  const void* tw = tw_ptr(c, b.dtype);
+  hipError_t e = timed(c, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, hat, tmp, 1, n * h, n2max, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, tmp, tmp, n, h, -1, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  const double scale = 1.0 / (static_cast<double>(n) * n * n);
+  return timed(c, XS21_K_ROWS_C2R, modes * 2 * rs + cells * store_size(storage), [&] {
+    return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, tw, kNtab, c->stream);
+  });
+}
+
+// Forward FFT and every smoothed box of the shared ladder of one box.
+hipError_t smooth_box(xs21_ctx* c, const BoxRec& b) {
+  unsigned char* hat = c->ws + c->lay.scratch;
+  unsigned char* tmp = hat + align_up(b.spec_bytes());
+  hipError_t e = forward3d(c, b, c->ws + b.off_delta, hat);
+  if (e != hipSuccess) return e;
+  for (int j = 0; j < b.nr(); ++j) {
+    void* out = c->ws + b.off_dR + static_cast<size_t>(j) * b.cells() * store_size(b.storage);
+    e = smooth3d(c, b, hat, tmp, b.n2max[j], b.storage, out);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Ionisation + dT_b + P(k) bins for `count` walkers whose tables are at
+// wc/thr, writing pk/xhi (device) with the given strides.  `scratch` is the
+// base of the spectra / partial-sum area.
+hipError_t eval_group(xs21_ctx* c, const BoxRec& b, unsigned char* scratch, const void* dR, int storage, int nr,
+                      const void* wc, const void* thr, int count, double* pk, long pk_stride, int nbins_out,
+                      double* xhi, long xhi_stride) {
+  const long n = b.n, h = static_cast<long>(b.half());
+  const double rs = static_cast<double>(real_size(b.dtype));
+  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  void* spec = scratch;
+  const long tiles = xs21::axis_tiles(b.n, n * h);
+  double* part = reinterpret_cast<double*>(scratch + align_up(count * b.spec_bytes()));
+  double* xpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) +
+                                            align_up(static_cast<size_t>(count) * tiles * b.nbins * 8));
+  const double tb = c->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+  const void* tw = tw_ptr(c, b.dtype);
+  hipError_t e = timed(c, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs, [&] {
+    return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_delta, nr, wc, thr, count, tb,
+                            c->phys.delta_c, spec, xpart, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, count * n, h, -1, tw, kNtab, c->stream);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
+    return xs21::launch_axis_bins(b.dtype, b.n, spec, count, n * h,
+                                  reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, part, tw, kNtab,
+                                  c->stream);
+  });
+  if (e != hipSuccess) return e;
+  const double L3 = b.box * b.box * b.box;
+  const double n6 = std::pow(static_cast<double>(n), 6);
+  const double pbytes = static_cast<double>(count) * (tiles * b.nbins + xs21::ion_grid(b.n)) * 8;
+  return timed(c, XS21_K_FINALIZE, pbytes, [&] {
+    return xs21::launch_finalize(count, part, tiles, b.nbins, xpart, xs21::ion_grid(b.n),
+                                 reinterpret_cast<const double*>(c->ws + b.off_counts), L3 / n6,
+                                 1.0 / cells, pk, pk_stride, nbins_out, xhi, xhi_stride, c->stream);
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xs21_last_error(void) { return g_error.c_str(); }
+
+xs21_status xs21_physics_default(xs21_physics* p) {
+  if (!p) return fail(XS21_EINVAL, "null physics");
+  std::memset(p, 0, sizeof *p);
+  p->delta_c = 1.686;
+  p->omega_m = 0.27;
+  p->omega_l = 0.73;
+  p->h = 0.7;
+  p->tb0_mK = 27.0;
+  p->pk_amp = 1.0;
+  p->pk_k0 = 0.05;
+  p->z_ref = 9.0;
+  p->radius_step = 1.1;
+  p->ladder_top = 20.0;
+  p->mu = 0.6;
+  p->mmin_form = 0;
+  g_error.clear();
+  return XS21_OK;
+}
+
+xs21_status xs21_create(xs21_ctx** out, int hip_device, void* hip_stream, const xs21_physics* phys) {
+  g_error.clear();
+  if (!out || !phys) return fail(XS21_EINVAL, "null argument");
+  *out = nullptr;
+  if (!xs21::plan::valid_physics(*phys)) return fail(XS21_EINVAL, "invalid physics constants");
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || hip_device < 0 || hip_device >= count)
+    return fail(XS21_EDEVICE, "device %d unavailable (%d devices): %s", hip_device, count, hipGetErrorString(e));
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return fail(XS21_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  auto* c = new (std::nothrow) xs21_ctx;
+  if (!c) return fail(XS21_ENOMEM, "host allocation failed");
+  c->device = hip_device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->phys = *phys;
+  e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(XS21_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return XS21_OK;
+}
+
+xs21_status xs21_destroy(xs21_ctx* ctx) {
+  g_error.clear();
+  if (!ctx) return XS21_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->upload_pending) (void)hipEventSynchronize(ctx->upload_done);
+  if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return XS21_OK;
+}
+
+xs21_status xs21_sync(xs21_ctx* ctx) {
+  g_error.clear();
+  xs21_status s = check_ctx(ctx);
+  if (s) return s;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_dtype dtype, int n, double box_mpc,
+                         double z, int n_bins, xs21_box* out) {
+  g_error.clear();
+  if (!ctx) return fail(XS21_EINVAL, "null context");
+  if (ctx->poisoned) return fail(XS21_ESTATE, "context poisoned");
+  if (ctx->prepared) return fail(XS21_ESTATE, "boxes must be added before xs21_prepare");
+  if (!delta || !out) return fail(XS21_EINVAL, "null argument");
+  if (dtype != XS21_F32 && dtype != XS21_F64) return fail(XS21_EINVAL, "box dtype must be F32 or F64");
+  if (!pow2_in_range(n)) return fail(XS21_EINVAL, "n = %d is not a power of two in [8, 512]", n);
+  if (!(std::isfinite(box_mpc) && box_mpc > 0)) return fail(XS21_EINVAL, "box side must be finite and > 0");
+  if (!(std::isfinite(z) && z > -1.0)) return fail(XS21_EINVAL, "redshift must be finite and > -1");
+  if (n_bins < 1 || n_bins > xs21::max_bins()) return fail(XS21_EINVAL, "n_bins must be in [1, %d]", xs21::max_bins());
+  BoxRec b;
+  b.n = n;
+  b.box = box_mpc;
+  b.z = z;
+  b.nbins = n_bins;
+  b.dtype = dtype;
+  b.radii = xs21::plan::ladder(ctx->phys.ladder_top, box_mpc / n, ctx->phys.radius_step);
+  if (b.nr() > xs21::max_radii())
+    return fail(XS21_EUNSUPPORTED, "ladder of %d radii exceeds %d", b.nr(), xs21::max_radii());
+  for (double r : b.radii) b.n2max.push_back(xs21::plan::n2max(r, box_mpc));
+  b.bintab = xs21::plan::bins(n, n_bins);
+  xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
+  if (on_device) {
+    b.dev_src = delta;
+  } else {
+    const size_t bytes = b.cells() * real_size(dtype);
+    try {
+      b.host.resize(bytes);
+    } catch (...) {
+      return fail(XS21_ENOMEM, "host copy of %zu bytes failed", bytes);
+    }
+    std::memcpy(b.host.data(), delta, bytes);
+    if (dtype == XS21_F32) {
+      const float* f = static_cast<const float*>(delta);
+      for (size_t i = 0; i < b.cells(); ++i)
+        if (!std::isfinite(f[i])) return fail(XS21_EINVAL, "non-finite density value at %zu", i);
+    } else {
+      const double* f = static_cast<const double*>(delta);
+      for (size_t i = 0; i < b.cells(); ++i)
+        if (!std::isfinite(f[i])) return fail(XS21_EINVAL, "non-finite density value at %zu", i);
+    }
+  }
+  ctx->boxes.push_back(std::move(b));
+  *out = static_cast<xs21_box>(ctx->boxes.size() - 1);
+  return XS21_OK;
+}
+
+xs21_status xs21_box_radii(xs21_ctx* ctx, xs21_box box, double* out, int cap, int* n_radii) {
+  g_error.clear();
+  if (!ctx || !n_radii) return fail(XS21_EINVAL, "null argument");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  const auto& r = ctx->boxes[box].radii;
+  *n_radii = static_cast<int>(r.size());
+  if (out)
+    for (int i = 0; i < std::min(cap, *n_radii); ++i) out[i] = r[i];
+  return XS21_OK;
+}
+
+xs21_status xs21_box_bins(xs21_ctx* ctx, xs21_box box, double* k_mean, double* counts) {
+  g_error.clear();
+  if (!ctx) return fail(XS21_EINVAL, "null context");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  const auto& b = ctx->boxes[box];
+  if (k_mean) std::copy(b.kmean.begin(), b.kmean.end(), k_mean);
+  if (counts) std::copy(b.counts.begin(), b.counts.end(), counts);
+  return XS21_OK;
+}
+
+xs21_status xs21_workspace_size(xs21_ctx* ctx, xs21_dtype storage, int max_walkers, int max_plain_radii,
+                                size_t* bytes) {
+  g_error.clear();
+  if (!ctx || !bytes) return fail(XS21_EINVAL, "null argument");
+  if (ctx->boxes.empty()) return fail(XS21_ESTATE, "no boxes registered");
+  if (storage != XS21_F32 && storage != XS21_BF16 && storage != XS21_F64)
+    return fail(XS21_EINVAL, "unknown storage type");
+  if (max_walkers < 1) return fail(XS21_EINVAL, "max_walkers must be >= 1");
+  if (max_plain_radii < 1 || max_plain_radii > xs21::max_radii())
+    return fail(XS21_EINVAL, "max_plain_radii must be in [1, %d]", xs21::max_radii());
+  for (const auto& b : ctx->boxes)
+    if (b.dtype == XS21_F32 && storage == XS21_F64)
+      return fail(XS21_EINVAL, "F64 storage needs F64 boxes");
+  const int group = std::min(max_walkers, xs21::max_group());
+  *bytes = compute_layout(ctx, storage, max_walkers, max_plain_radii, group, ctx->boxes).total;
+  return XS21_OK;
+}
+
+xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtype storage, int max_walkers,
+                         int max_plain_radii) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (ctx->prepared) return fail(XS21_ESTATE, "already prepared");
+  size_t need = 0;
+  if (xs21_status s = xs21_workspace_size(ctx, storage, max_walkers, max_plain_radii, &need)) return s;
+  if (!workspace) return fail(XS21_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(XS21_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < need) return fail(XS21_ENOMEM, "workspace holds %zu bytes, %zu needed", bytes, need);
+  ctx->ws = static_cast<unsigned char*>(workspace);
+  ctx->ws_bytes = bytes;
+  ctx->storage = storage;
+  ctx->max_walkers = max_walkers;
+  ctx->max_plain = max_plain_radii;
+  ctx->group = std::min(max_walkers, xs21::max_group());
+  ctx->lay = compute_layout(ctx, storage, max_walkers, max_plain_radii, ctx->group, ctx->boxes);
+
+  // pinned staging for walker tables
+  ctx->pinned_bytes = std::max<size_t>(ctx->lay.tables_bytes, ctx->lay.one_table_bytes);
+  HIPCHECK(ctx, hipHostMalloc(&ctx->pinned, ctx->pinned_bytes, hipHostMallocDefault));
+
+  const auto tw = xs21::plan::twiddles(kNtab);
+  std::vector<float> tw32(tw.begin(), tw.end());
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tw64, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  for (auto& b : ctx->boxes) {
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_bintab, b.bintab.data(), b.bintab.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_counts, b.counts.data(), b.nbins * 8, hipMemcpyHostToDevice, ctx->stream));
+    const size_t dbytes = b.cells() * real_size(b.dtype);
+    if (b.dev_src)
+      HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.dev_src, dbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+      HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.host.data(), dbytes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, smooth_box(ctx, b));
+  }
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& b : ctx->boxes) {
+    std::vector<unsigned char>().swap(b.host);
+    b.dev_src = nullptr;
+  }
+  ctx->prepared = true;
+  return XS21_OK;
+}
+
+xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers, int nw,
+                            double* pk, double* xhi_mean) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (!boxes || nb < 1 || !walkers || nw < 1) return fail(XS21_EINVAL, "empty batch");
+  if (nb > static_cast<int>(ctx->boxes.size())) return fail(XS21_EINVAL, "more listed boxes than registered");
+  int nbmax = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (xs21_status s = check_box(ctx, boxes[i])) return s;
+    if (ctx->boxes[boxes[i]].dtype != ctx->boxes[boxes[0]].dtype)
+      return fail(XS21_EINVAL, "boxes of one batch must share a dtype");
+    nbmax = std::max(nbmax, ctx->boxes[boxes[i]].nbins);
+    for (int k = 0; k < i; ++k)
+      if (boxes[k] == boxes[i]) return fail(XS21_EINVAL, "box %d listed twice", boxes[i]);
+  }
+  for (int w = 0; w < nw; ++w)
+    if (!xs21::plan::valid_walker(walkers[w])) return fail(XS21_EINVAL, "walker %d has invalid parameters", w);
+
+  for (int w0 = 0; w0 < nw; w0 += ctx->max_walkers) {
+    const int cnt = std::min(ctx->max_walkers, nw - w0);
+    if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
+    // host planning for every (walker, box) of this chunk
+    size_t off = 0;
+    std::vector<size_t> boff(nb);
+    for (int i = 0; i < nb; ++i) {
+      const BoxRec& b = ctx->boxes[boxes[i]];
+      boff[i] = off;
+      build_tables(ctx->phys, b, walkers + w0, cnt, false, b.radii, static_cast<unsigned char*>(ctx->pinned) + off,
+                   ctx->max_walkers);
+      off += b.table_bytes(ctx->max_walkers);
+    }
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tables, ctx->pinned, off, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+    ctx->upload_pending = true;
+    for (int i = 0; i < nb; ++i) {
+      const BoxRec& b = ctx->boxes[boxes[i]];
+      const unsigned char* wc = ctx->ws + ctx->lay.tables + boff[i];
+      const unsigned char* thr = wc + align_up(ctx->max_walkers * b.wc_size());
+      for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
+        const int g = std::min(ctx->group, cnt - g0);
+        const long wg = w0 + g0;
+        double* pk_out = pk ? pk + (wg * nb + i) * nbmax : nullptr;
+        double* xh_out = xhi_mean ? xhi_mean + wg * nb + i : nullptr;
+        HIPCHECK(ctx, eval_group(ctx, b, ctx->ws + ctx->lay.scratch, ctx->ws + b.off_dR, b.storage, b.nr(),
+                                 wc + g0 * b.wc_size(),
+                                 thr + static_cast<size_t>(g0) * b.nr() * real_size(b.dtype), g, pk_out,
+                                 static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
+      }
+    }
+  }
+  return XS21_OK;
+}
+
+xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, const double* radii, int n_radii,
+                      void* x_hi, void* dtb, double* pk, double* k_mean, double* counts, double* xhi_mean) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!walker || !xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  const BoxRec& b = ctx->boxes[box];
+  std::vector<double> r;
+  if (radii) {
+    if (n_radii < 1) return fail(XS21_EINVAL, "n_radii must be >= 1");
+    r.assign(radii, radii + n_radii);
+    for (int j = 0; j < n_radii; ++j) {
+      if (!(std::isfinite(r[j]) && r[j] > 0)) return fail(XS21_EINVAL, "radius %d not finite and > 0", j);
+      if (j && !(r[j] < r[j - 1])) return fail(XS21_EINVAL, "radii must decrease");
+    }
+  } else {
+    r = xs21::plan::ladder(walker->r_mfp, b.box / b.n, ctx->phys.radius_step);
+  }
+  const int nr = static_cast<int>(r.size());
+  if (nr > ctx->max_plain) return fail(XS21_ENOMEM, "%d radii exceed max_plain_radii = %d", nr, ctx->max_plain);
+
+  // literal per-walker method: forward FFT and every smoothed box recomputed
+  unsigned char* s = ctx->ws + ctx->lay.scratch;
+  unsigned char* hat = s;
+  unsigned char* tmp = hat + align_up(b.spec_bytes());
+  unsigned char* dR = tmp + align_up(b.spec_bytes());
+  unsigned char* eval_area = dR + align_up(static_cast<size_t>(ctx->max_plain) * b.cells() * real_size(b.dtype));
+  HIPCHECK(ctx, forward3d(ctx, b, ctx->ws + b.off_delta, hat));
+  for (int j = 0; j < nr; ++j)
+    HIPCHECK(ctx, smooth3d(ctx, b, hat, tmp, xs21::plan::n2max(r[j], b.box), b.dtype,
+                           dR + static_cast<size_t>(j) * b.cells() * real_size(b.dtype)));
+
+  if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
+  build_tables(ctx->phys, b, walker, 1, true, r, static_cast<unsigned char*>(ctx->pinned), 1);
+  const size_t tb_bytes = align_up(b.wc_size()) + align_up(nr * real_size(b.dtype));
+  unsigned char* wc = ctx->ws + ctx->lay.one_table;
+  HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+  ctx->upload_pending = true;
+  const unsigned char* thr = wc + align_up(b.wc_size());
+
+  // the eval scratch of a plain call sits after the plain smoothed boxes
+  double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
+  HIPCHECK(ctx, eval_group(ctx, b, eval_area, dR, b.dtype, nr, wc, thr, 1, outs, b.nbins, b.nbins, outs + 128, 1));
+  if (x_hi || dtb) {
+    // fields through the same per-cell arithmetic; staged in the hat/tmp area
+    const size_t fbytes = b.cells() * real_size(b.dtype);
+    if (2 * align_up(fbytes) > 2 * align_up(b.spec_bytes()))
+      return fail(XS21_EUNSUPPORTED, "field staging does not fit");
+    void* fx = hat;
+    void* fd = hat + align_up(fbytes);
+    const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+    HIPCHECK(ctx, timed(ctx, XS21_K_OTHER, 0.0, [&] {
+      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_delta, nr, wc, thr, tbv,
+                                      ctx->phys.delta_c, fx, fd, ctx->stream);
+    }));
+    if (x_hi) HIPCHECK(ctx, hipMemcpyAsync(x_hi, fx, fbytes, hipMemcpyDeviceToHost, ctx->stream));
+    if (dtb) HIPCHECK(ctx, hipMemcpyAsync(dtb, fd, fbytes, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  double host_out[129];
+  HIPCHECK(ctx, hipMemcpyAsync(host_out, outs, 129 * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->upload_pending = false;
+  if (pk) std::copy(host_out, host_out + b.nbins, pk);
+  if (xhi_mean) *xhi_mean = host_out[128];
+  if (k_mean) std::copy(b.kmean.begin(), b.kmean.end(), k_mean);
+  if (counts) std::copy(b.counts.begin(), b.counts.end(), counts);
+  return XS21_OK;
+}
+
+xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, void* x_hi, void* dtb) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!walker || !xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  const BoxRec& b = ctx->boxes[box];
+  if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
+  build_tables(ctx->phys, b, walker, 1, false, b.radii, static_cast<unsigned char*>(ctx->pinned), 1);
+  const size_t tb_bytes = align_up(b.wc_size()) + align_up(b.nr() * real_size(b.dtype));
+  unsigned char* wc = ctx->ws + ctx->lay.one_table;
+  HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+  ctx->upload_pending = true;
+  const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+  HIPCHECK(ctx, timed(ctx, XS21_K_OTHER, 0.0, [&] {
+    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_delta, b.nr(), wc,
+                                    wc + align_up(b.wc_size()), tbv, ctx->phys.delta_c, x_hi, dtb, ctx->stream);
+  }));
+  return XS21_OK;
+}
+
+xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  const BoxRec& b = ctx->boxes[box];
+  if (index < 0 || index >= b.nr()) return fail(XS21_EINVAL, "radius index %d out of range", index);
+  if (!out) return fail(XS21_EINVAL, "null output");
+  const void* src = ctx->ws + b.off_dR + static_cast<size_t>(index) * b.cells() * store_size(b.storage);
+  HIPCHECK(ctx, xs21::launch_cast(b.dtype, b.storage, src, out, b.cells(), ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!field || !pk) return fail(XS21_EINVAL, "null argument");
+  const BoxRec& b = ctx->boxes[box];
+  const long n = b.n, h = static_cast<long>(b.half());
+  unsigned char* s = ctx->ws + ctx->lay.scratch;
+  const long tiles = xs21::axis_tiles(b.n, n * h);
+  double* part = reinterpret_cast<double*>(s + align_up(b.spec_bytes()));
+  double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
+  HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, s, n * n, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, s, s, n, h, -1, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, n * h, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
+                                       b.nbins, part, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
+  const double L3 = b.box * b.box * b.box;
+  HIPCHECK(ctx, xs21::launch_finalize(1, part, tiles, b.nbins, nullptr, 0,
+                                      reinterpret_cast<const double*>(ctx->ws + b.off_counts),
+                                      L3 / std::pow(static_cast<double>(n), 6), 1.0, outs, b.nbins, b.nbins, nullptr,
+                                      0, ctx->stream));
+  HIPCHECK(ctx, hipMemcpyAsync(pk, outs, b.nbins * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_resmooth(xs21_ctx* ctx, xs21_box box, const void* new_delta) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  const BoxRec& b = ctx->boxes[box];
+  if (new_delta)
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, new_delta, b.cells() * real_size(b.dtype),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHECK(ctx, smooth_box(ctx, b));
+  return XS21_OK;
+}
+
+xs21_status xs21_profile(xs21_ctx* ctx, int enable) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (enable) {
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& r : ctx->pending) {
+      ctx->pool.push_back(r.a);
+      ctx->pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < XS21_K_COUNT; ++k) ctx->tot_ms[k] = ctx->tot_bytes[k] = 0.0, ctx->launches[k] = 0;
+  }
+  ctx->prof = enable != 0;
+  return XS21_OK;
+}
+
+xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (kind < 0 || kind >= XS21_K_COUNT) return fail(XS21_EINVAL, "unknown kernel class %d", kind);
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& r : ctx->pending) {
+    float ms = 0.f;
+    HIPCHECK(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+    ctx->tot_ms[r.kind] += ms;
+    ctx->launches[r.kind] += 1;
+    ctx->tot_bytes[r.kind] += r.bytes;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  if (total_ms) *total_ms = ctx->tot_ms[kind];
+  if (launches) *launches = ctx->launches[kind];
+  if (bytes) *bytes = ctx->tot_bytes[kind];
+  return XS21_OK;
+}
+
+// ------------------------------------------------------------ host planning
+
+xs21_status xs21_plan_ladder(double r_top, double r_cell, double step, double* out, int cap, int* n_radii) {
+  g_error.clear();
+  if (!n_radii) return fail(XS21_EINVAL, "null argument");
+  if (!(std::isfinite(r_top) && r_top > 0 && std::isfinite(r_cell) && r_cell > 0 && std::isfinite(step) && step > 1))
+    return fail(XS21_EINVAL, "invalid ladder parameters");
+  const auto r = xs21::plan::ladder(r_top, r_cell, step);
+  *n_radii = static_cast<int>(r.size());
+  if (out)
+    for (int i = 0; i < std::min(cap, *n_radii); ++i) out[i] = r[i];
+  return XS21_OK;
+}
+
+xs21_status xs21_plan_sigma2(const xs21_physics* phys, double radius, double z, double* out) {
+  g_error.clear();
+  if (!phys || !out) return fail(XS21_EINVAL, "null argument");
+  if (!xs21::plan::valid_physics(*phys)) return fail(XS21_EINVAL, "invalid physics constants");
+  if (!(std::isfinite(radius) && radius > 0 && std::isfinite(z) && z > -1)) return fail(XS21_EINVAL, "invalid R or z");
+  *out = xs21::plan::sigma2(*phys, radius, z);
+  return XS21_OK;
+}
+
+xs21_status xs21_plan_walker(const xs21_physics* phys, double z, const double* radii, int n_radii,
+                             const xs21_walker* walker, double* thr, double* dsig2, int* first, double* m_min) {
+  g_error.clear();
+  if (!phys || !radii || !walker) return fail(XS21_EINVAL, "null argument");
+  if (!xs21::plan::valid_physics(*phys)) return fail(XS21_EINVAL, "invalid physics constants");
+  if (!xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  if (n_radii < 1 || !(std::isfinite(z) && z > -1)) return fail(XS21_EINVAL, "invalid radii count or z");
+  const auto wp = xs21::plan::walker(*phys, z, radii, n_radii, *walker);
+  if (thr) std::copy(wp.thr.begin(), wp.thr.end(), thr);
+  if (dsig2) std::copy(wp.dsig2.begin(), wp.dsig2.end(), dsig2);
+  if (first) *first = wp.first;
+  if (m_min) *m_min = wp.m_min;
+  return XS21_OK;
+}
+
+xs21_status xs21_plan_bins(int n, int n_bins, int8_t* out) {
+  g_error.clear();
+  if (!out) return fail(XS21_EINVAL, "null argument");
+  if (!pow2_in_range(n)) return fail(XS21_EINVAL, "n = %d is not a power of two in [8, 512]", n);
+  if (n_bins < 1 || n_bins > xs21::max_bins()) return fail(XS21_EINVAL, "n_bins out of range");
+  const auto t = xs21::plan::bins(n, n_bins);
+  std::copy(t.begin(), t.end(), out);
+  return XS21_OK;
+}
+
+}  // extern "C"

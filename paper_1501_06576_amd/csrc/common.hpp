@@ -1,0 +1,65 @@
+// Shared device/host types: complex numbers, bf16 storage, storage loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xs21 {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// bf16 stored as raw 16-bit patterns (upper half of an IEEE binary32).
+struct bf16 {
+  uint16_t bits;
+};
+
+__host__ __device__ __forceinline__ float bf16_to_f32(bf16 v) {
+  return __builtin_bit_cast(float, static_cast<uint32_t>(v.bits) << 16);
+}
+
+// Round to nearest, ties to even; NaN stays NaN.
+__host__ __device__ __forceinline__ bf16 f32_to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return bf16{static_cast<uint16_t>((u >> 16) | 0x40u)};
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return bf16{static_cast<uint16_t>(u >> 16)};
+}
+
+// Load a stored smoothed-box value as the working type T.
+template <typename T, typename S>
+__host__ __device__ __forceinline__ T load_as(const S* p, size_t i) { return static_cast<T>(p[i]); }
+template <>
+__host__ __device__ __forceinline__ float load_as<float, bf16>(const bf16* p, size_t i) { return bf16_to_f32(p[i]); }
+
+template <typename S, typename T>
+__host__ __device__ __forceinline__ void store_as(S* p, size_t i, T v) { p[i] = static_cast<S>(v); }
+template <>
+__host__ __device__ __forceinline__ void store_as<bf16, float>(bf16* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
+
+// Per-(walker, box) constants consumed by the per-cell ionisation pass.
+template <typename T>
+struct WalkerConst {
+  T zeta;      // ionising efficiency
+  T a_cell;    // 1 / sqrt(2 (sigma^2(M_min) - sigma^2(R_cell))), valid if partial != 0
+  int32_t first;    // first radius index the walker filters at (R <= R_mfp)
+  int32_t partial;  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged
+};
+
+}  // namespace xs21

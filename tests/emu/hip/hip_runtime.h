@@ -1,0 +1,124 @@
+// CPU emulation of the subset of HIP that the xs21 sources use.
+//
+// TEST INFRASTRUCTURE ONLY: lets the unmodified kernel and host sources build
+// with g++ (+ AddressSanitizer) so that indexing, bounds and synchronisation
+// logic can be checked on a machine without a GPU.  Every GPU thread of a
+// block runs as an OS thread; __syncthreads is a barrier over the block and
+// wave intrinsics exchange values through a per-wave slot array.  Blocks run
+// one after another, so __shared__ maps to function-static storage.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+#include <utility>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+
+typedef int hipError_t;
+enum {
+  hipSuccess = 0,
+  hipErrorInvalidValue = 1,
+  hipErrorOutOfMemory = 2,
+  hipErrorNoDevice = 100,
+  hipErrorLaunchFailure = 719
+};
+typedef void* hipStream_t;
+typedef struct hipemu_event* hipEvent_t;
+typedef enum { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
+               hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
+#define hipEventDisableTiming 2u
+#define hipHostMallocDefault 0u
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+namespace hipemu {
+struct idx3 { unsigned x, y, z; };
+extern thread_local idx3 tl_thread;
+extern thread_local idx3 tl_block;
+extern dim3 g_grid, g_block;
+void syncthreads();
+void wave_exchange(const void* in, void* out, size_t bytes, int src_lane);
+int lane_id();
+void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg);
+hipError_t last_error(hipError_t set = -1);
+}  // namespace hipemu
+
+#define threadIdx (::hipemu::tl_thread)
+#define blockIdx (::hipemu::tl_block)
+#define gridDim (::hipemu::g_grid)
+#define blockDim (::hipemu::g_block)
+
+inline void __syncthreads() { ::hipemu::syncthreads(); }
+
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  (void)width;
+  T r;
+  ::hipemu::wave_exchange(&v, &r, sizeof(T), ::hipemu::lane_id() ^ mask);
+  return r;
+}
+
+using std::max;
+using std::min;
+
+namespace hipemu {
+template <typename F, typename Tuple>
+struct Launch {
+  F f;
+  Tuple args;
+  static void body(void* p) {
+    auto* self = static_cast<Launch*>(p);
+    std::apply(self->f, self->args);
+  }
+};
+
+template <typename... KArgs, typename... Args>
+inline hipError_t launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t, hipStream_t, Args&&... args) {
+  if (block.x * block.y * block.z > 1024 || block.y != 1 || block.z != 1 || grid.z != 1 || grid.x == 0 || grid.y == 0)
+    return last_error(hipErrorInvalidValue);
+  using Tup = std::tuple<KArgs...>;
+  Launch<void (*)(KArgs...), Tup> l{k, Tup(static_cast<KArgs>(args)...)};
+  run_grid(grid, block, &Launch<void (*)(KArgs...), Tup>::body, &l);
+  return hipSuccess;
+}
+}  // namespace hipemu
+
+#define hipLaunchKernelGGL(kernel, grid, block, shmem, stream, ...) \
+  (void)::hipemu::launch(kernel, dim3(grid), dim3(block), shmem, stream, ##__VA_ARGS__)
+
+extern "C++" {
+hipError_t hipGetLastError();
+const char* hipGetErrorString(hipError_t e);
+hipError_t hipGetDeviceCount(int* n);
+hipError_t hipSetDevice(int d);
+hipError_t hipMalloc(void** p, size_t bytes);
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipDeviceSynchronize();
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t hipEventDestroy(hipEvent_t e);
+}

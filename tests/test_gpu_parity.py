@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Tolerances: flipped-cell fraction <= 1e-4 and per-bin P(k) relative error
+<= 1e-3 for the FP32 path; the FP64 path is held to 1e-9.  Integer outputs
+(bin counts) must match exactly.  Every input is seeded and synthetic.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+AMP = synth.reference_amplitude()
+PHYS = oracle.Physics(pk_amp=AMP)
+
+
+@pytest.fixture(scope="module")
+def xs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_06576_amd as mod
+    if not os.path.exists(mod.LIB_PATH):
+        from paper_1501_06576_amd import build
+        build.build()
+    mod.library()
+    return mod
+
+
+def _ctx(xs, **phys):
+    return xs.Context(0, phys=xs.physics(pk_amp=AMP, **phys))
+
+
+def report(tag, x_gpu, ev, pk_gpu, xm_gpu):
+    flips = float(np.mean((np.asarray(x_gpu) == 0) != ev.flagged)) if x_gpu is not None else 0.0
+    ok = ev.counts > 0
+    rel = np.abs(pk_gpu[ok] / ev.pk[ok] - 1.0)
+    line = (f"[{tag}] flips={flips:.2e} pk_rel_max={rel.max():.2e} xhi_mean gpu={xm_gpu:.8f} "
+            f"orc={ev.xhi_mean:.8f}")
+    if x_gpu is not None:
+        same = (np.asarray(x_gpu) == 0) == ev.flagged
+        line += f" max|dx_HI|={np.abs(np.asarray(x_gpu, dtype=np.float64) - ev.x_hi)[same].max():.2e}"
+    print(line, flush=True)
+    return flips, rel.max()
+
+
+# ------------------------------------------------------------------ plain path
+
+def test_plain_f64_64(xs):
+    """64^3, 128 Mpc, z = 9, FP64 on both sides."""
+    n, box, z, nb = 64, 128.0, 9.0, 12
+    w = (30.0, 15.0, 5e4)
+    d = synth.make_box(n, box, z, seed=synth.BOX_SEEDS[(64, 128.0)], amp=AMP, dtype=np.float64)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f64", max_walkers=1, max_plain_radii=30)
+    radii = oracle.plain_radii(w[1], n, box, PHYS)
+    out = ctx.eval(b, w, radii=radii)
+    ev = oracle.evaluate(d, box, z, w, radii, nb, PHYS)
+    flips, rel = report("plain-f64-64", out["x_hi"], ev, out["pk"], out["xhi_mean"])
+    assert flips == 0.0
+    assert rel <= 1e-9
+    same = (out["x_hi"] == 0) == ev.flagged
+    assert np.abs(out["x_hi"] - ev.x_hi)[same].max() <= 1e-10
+    assert np.abs(out["dtb"] - ev.dtb)[same].max() <= 1e-8
+    assert abs(out["xhi_mean"] - ev.xhi_mean) <= 1e-10
+    np.testing.assert_array_equal(out["counts"], ev.counts)
+    np.testing.assert_allclose(out["k_mean"], ev.k_mean, rtol=1e-12)
+    # default radius list = the plain ladder from R_mfp
+    out2 = ctx.eval(b, w, fields=False)
+    np.testing.assert_array_equal(out2["pk"], out["pk"])
+    ctx.close()
+
+
+def test_plain_f32_128_three_redshifts(xs):
+    """128^3, 250 Mpc, z = 8, 9, 10, FP32 path, one parameter set."""
+    wl = synth.WORKLOADS["plain-f32-128"]
+    boxes = synth.workload_boxes(wl, AMP)
+    w = wl.walkers[0]
+    ctx = _ctx(xs)
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    ctx.prepare("f32", max_walkers=1, max_plain_radii=30)
+    for h, d, s in zip(hs, boxes, wl.boxes):
+        radii = oracle.plain_radii(w[1], s.n, s.box_mpc, PHYS)
+        out = ctx.eval(h, w, radii=radii)
+        ev = oracle.evaluate(d, s.box_mpc, s.z, w, radii, s.n_bins, PHYS)
+        flips, rel = report(f"plain-f32-128 z={s.z}", out["x_hi"], ev, out["pk"], out["xhi_mean"])
+        assert flips <= 1e-4
+        assert rel <= 1e-3
+        assert abs(out["xhi_mean"] - ev.xhi_mean) <= 1e-4
+        np.testing.assert_array_equal(out["counts"], ev.counts)
+    ctx.close()
+
+
+# ------------------------------------------------------------------ batched path
+
+EDGE_WALKERS = [
+    (30.0, 15.0, 5e4),      # fiducial-like
+    (100.0, 20.0, 1e4),     # nearly fully ionised
+    (5.0, 5.0, 1e6),        # nearly neutral
+    (0.4, 12.0, 2e4),       # zeta < 1/2: no cell can be flagged
+    (60.0, 1.0, 3e4),       # R_mfp below every ladder radius: cell radius only
+    (17.3, 7.7, 2.2e5),
+    (45.0, 19.9, 1.5e4),
+    (8.0, 11.0, 6e5),
+    (25.0, 20.0, 8e4),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batched_small_vs_oracle(xs, dtype):
+    """N = 64 (several tiles, ragged walker groups) against the oracle for each walker."""
+    n, box, z, nb = 64, 128.0, 8.5, 12
+    npd = np.float64 if dtype == "f64" else np.float32
+    d = synth.make_box(n, box, z, seed=41, amp=AMP, dtype=npd)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare(dtype, max_walkers=4, max_plain_radii=30)   # 9 walkers -> 3 chunks, ragged last
+    pk, xhi = ctx.eval_batch([b], EDGE_WALKERS)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    shared = ctx.radii(b)
+    assert shared == pytest.approx(oracle.shared_radii(n, box, PHYS), rel=1e-15)
+    for i, w in enumerate(EDGE_WALKERS):
+        ev = oracle.evaluate(d, box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+        x, _ = ctx.materialize(b, w)
+        flips, rel = report(f"batched-{dtype} w{i}", x.cpu().numpy(), ev, pk[i, 0], xhi[i, 0])
+        if dtype == "f64":
+            assert flips == 0.0 and rel <= 1e-9
+            assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-10
+        else:
+            assert flips <= 1e-4 and rel <= 1e-3
+            assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-4
+        if w[0] < 0.5:
+            assert not (x.cpu().numpy() == 0).any()
+    ctx.close()
+
+
+def test_smoothed_boxes(xs):
+    """delta_R for every ladder radius against the oracle's sharp-k smoothing."""
+    for dtype, n, box, tol in (("f64", 32, 64.0, 1e-12), ("f32", 64, 128.0, 2e-6)):
+        npd = np.float64 if dtype == "f64" else np.float32
+        d = synth.make_box(n, box, 9.0, seed=43, amp=AMP, dtype=npd)
+        ctx = _ctx(xs)
+        b = ctx.add_box(d, box, 9.0, 6)
+        ctx.prepare(dtype, max_walkers=1, max_plain_radii=30)
+        dh = np.fft.rfftn(d.astype(np.float64))
+        scale = float(np.abs(d).max())
+        worst = 0.0
+        for j, r in enumerate(ctx.radii(b)):
+            got = ctx.smoothed(b, j).cpu().numpy().astype(np.float64)
+            ref = oracle.smooth(dh, n, box, r)
+            worst = max(worst, float(np.abs(got - ref).max()) / scale)
+        print(f"[smoothed {dtype} n={n}] max |err| / max|delta| = {worst:.2e}", flush=True)
+        assert worst <= tol
+        ctx.close()
+
+
+@pytest.mark.parametrize("dtype,n", [("f64", 32), ("f32", 64), ("f32", 16)])
+def test_power_spectrum_plane_wave(xs, dtype, n):
+    """A single plane wave puts a^2 L^3 / (2 c_b) into its own bin and nothing elsewhere."""
+    import torch
+    box, nb, amp = 50.0, 6, 1.7
+    m = (1, 2, 3) if n > 16 else (1, 0, 2)
+    g = np.indices((n, n, n))
+    f = amp * np.cos(2 * np.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n)
+    npd = np.float64 if dtype == "f64" else np.float32
+    ctx = _ctx(xs)
+    b = ctx.add_box(np.zeros((n, n, n), dtype=npd), box, 9.0, nb)
+    ctx.prepare(dtype, max_walkers=1, max_plain_radii=30)
+    pk = ctx.power_spectrum(b, torch.from_numpy(f.astype(npd)).cuda())
+    _, counts = ctx.bins(b)
+    bi = oracle.bin_of_n2(sum(v * v for v in m), n, nb)
+    expect = np.zeros(nb)
+    expect[bi] = amp ** 2 * box ** 3 / (2 * counts[bi])
+    tol = 1e-10 if dtype == "f64" else 2e-5
+    np.testing.assert_allclose(pk, expect, rtol=tol, atol=tol * expect.max())
+    ctx.close()
+
+
+def test_uniform_box(xs):
+    """delta = c everywhere: dT_b is uniform, so every bin has zero power."""
+    n, box, z = 32, 64.0, 9.0
+    d = np.full((n, n, n), 0.25, dtype=np.float32)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, 5)
+    ctx.prepare("f32", max_walkers=4, max_plain_radii=30)
+    walkers = [(20.0, 15.0, 3e4), (1e9, 10.0, 1e4), (2.0, 10.0, 1e5)]
+    pk, xhi = ctx.eval_batch([b], walkers)
+    pk = pk.cpu().numpy()
+    assert np.all(np.abs(pk) <= 1e-6 * (27.0 ** 2) * box ** 3 / n ** 3)
+    assert xhi.cpu().numpy()[1, 0] == 0.0     # every cell flagged
+    ev = oracle.evaluate(d, box, z, walkers[2], oracle.walker_radii(ctx.radii(b), 10.0), 5, PHYS)
+    assert xhi.cpu().numpy()[2, 0] == pytest.approx(ev.xhi_mean, abs=1e-6)
+    ctx.close()
+
+
+def test_batched_equals_plain_and_deterministic(xs):
+    """A batched walker equals a plain evaluation on the same radius list; reruns are bitwise equal."""
+    n, box, z, nb = 64, 128.0, 9.0, 12
+    d = synth.make_box(n, box, z, seed=44, amp=AMP, dtype=np.float32)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f32", max_walkers=16, max_plain_radii=30)
+    walkers = synth.draw_walkers(16, 7)
+    pk1, x1 = ctx.eval_batch([b], walkers)
+    pk2, x2 = ctx.eval_batch([b], walkers)
+    assert np.array_equal(pk1.cpu().numpy(), pk2.cpu().numpy())
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    shared = ctx.radii(b)
+    for i in (0, 5, 11):
+        w = walkers[i]
+        out = ctx.eval(b, w, radii=oracle.walker_radii(shared, w[1]), fields=False)
+        np.testing.assert_allclose(out["pk"], pk1.cpu().numpy()[i, 0], rtol=1e-6)
+        assert out["xhi_mean"] == pytest.approx(x1.cpu().numpy()[i, 0], abs=1e-6)
+    ctx.close()
+
+
+def test_monotonicity(xs):
+    """x_HI per cell: non-increasing in zeta and R_mfp, non-decreasing in T_vir."""
+    n, box, z = 64, 128.0, 9.0
+    d = synth.make_box(n, box, z, seed=45, amp=AMP, dtype=np.float32)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, 8)
+    ctx.prepare("f32", max_walkers=4, max_plain_radii=30)
+    base = ctx.materialize(b, (20.0, 10.0, 3e4))[0].cpu().numpy()
+    assert np.all(ctx.materialize(b, (40.0, 10.0, 3e4))[0].cpu().numpy() <= base)
+    assert np.all(ctx.materialize(b, (20.0, 18.0, 3e4))[0].cpu().numpy() <= base)
+    assert np.all(ctx.materialize(b, (20.0, 10.0, 1e5))[0].cpu().numpy() >= base)
+    ctx.close()
+
+
+# ------------------------------------------------------------------ full sizes
+
+def test_batched_256_full_size(xs):
+    """256^3 x 3 z with 64 walkers (the benchmark launch configuration); sampled oracle checks."""
+    import torch
+    wl = synth.WORKLOADS["batched-256"]
+    boxes = synth.workload_boxes(wl, AMP)
+    walkers = synth.workload_walkers(wl)
+    ctx = _ctx(xs)
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    ctx.prepare("f32", max_walkers=64, max_plain_radii=40)
+    pk, xhi = ctx.eval_batch(hs, walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    assert np.isfinite(pk).all() and np.all((xhi >= 0) & (xhi <= 1))
+    shared = ctx.radii(hs[1])
+    # sampled walkers on the z = 9 box, checked cell by cell and bin by bin
+    for i in (3, 40):
+        w = walkers[i]
+        ev = oracle.evaluate(boxes[1], 250.0, 9.0, w, oracle.walker_radii(shared, w[1]), 15, PHYS)
+        x, _ = ctx.materialize(hs[1], w)
+        flips, rel = report(f"batched-256 w{i} z=9", x.cpu().numpy(), ev, pk[i, 1], xhi[i, 1])
+        assert flips <= 1e-4 and rel <= 1e-3
+        assert abs(xhi[i, 1] - ev.xhi_mean) <= 1e-4
+    ctx.close()
+    torch.cuda.synchronize()
+
+
+def test_uneven_bf16_storage(xs):
+    """128^3/250 Mpc and 256^3/300 Mpc boxes at z = 8, 9, 10 with BF16 smoothed boxes.
+
+    BF16 storage is reported against the FP64 oracle and held to loose bounds
+    only (rounding delta_R to 8 mantissa bits moves cells across thresholds).
+    """
+    wl = synth.WORKLOADS["uneven-mix"]
+    boxes = synth.workload_boxes(wl, AMP)
+    walkers = synth.workload_walkers(wl)[:32]
+    ctx = _ctx(xs)
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    ctx.prepare("bf16", max_walkers=32, max_plain_radii=40)
+    pk, xhi = ctx.eval_batch(hs, walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    for bi in (0, 4):
+        s = wl.boxes[bi]
+        w = walkers[2]
+        ev = oracle.evaluate(boxes[bi], s.box_mpc, s.z, w, oracle.walker_radii(ctx.radii(hs[bi]), w[1]),
+                             s.n_bins, PHYS)
+        x, _ = ctx.materialize(hs[bi], w)
+        flips, rel = report(f"uneven-bf16 box{bi}", x.cpu().numpy(), ev, pk[2, bi], xhi[2, bi])
+        assert flips <= 2e-2 and rel <= 5e-2
+    ctx.close()
