@@ -59,11 +59,12 @@ struct BoxRec {
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
   size_t half() const { return static_cast<size_t>(n / 2 + 1); }
-  size_t spec_bytes() const { return static_cast<size_t>(n) * n * half() * 2 * real_size(dtype); }
+  size_t pitch() const { return static_cast<size_t>(xs21::half_pitch(n)); }
+  size_t spec_bytes() const { return static_cast<size_t>(n) * n * pitch() * 2 * real_size(dtype); }
   int nr() const { return static_cast<int>(radii.size()); }
   size_t wc_size() const { return dtype == xs21::kF64 ? sizeof(WalkerConst<double>) : sizeof(WalkerConst<float>); }
   size_t table_bytes(int walkers) const {
-    return align_up(walkers * wc_size()) + align_up(static_cast<size_t>(walkers) * nr() * real_size(dtype));
+    return align_up(walkers * wc_size()) + align_up(static_cast<size_t>(walkers) * xs21::thr_stride() * real_size(dtype));
   }
 };
 
@@ -172,7 +173,7 @@ int box_storage(const BoxRec& b, int storage) { return b.dtype == xs21::kF64 ? x
 size_t prepare_scratch(const BoxRec& b) { return 2 * align_up(b.spec_bytes()); }
 
 size_t eval_scratch(const BoxRec& b, int group) {
-  const long tiles = xs21::axis_tiles(b.n, static_cast<long>(b.n) * b.half());
+  const long tiles = xs21::axis_tiles(b.n, static_cast<long>(b.n) * b.pitch());
   return align_up(group * b.spec_bytes()) + align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
          align_up(static_cast<size_t>(group) * xs21::ion_grid(b.n) * 8);
 }
@@ -202,7 +203,7 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     b.off_dR = off;
     off += align_up(static_cast<size_t>(b.nr()) * b.cells() * store_size(b.storage));
     tables += b.table_bytes(max_walkers);
-    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(std::max(max_plain, b.nr()) * 8));
+    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(xs21::thr_stride() * 8));
     scratch = std::max({scratch, prepare_scratch(b), eval_scratch(b, group), plain_scratch(b, max_plain)});
   }
   (void)c;
@@ -221,6 +222,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
   return L;
 }
 
+// Walker constants and its thresholds padded to thr_stride() entries: +inf
+// before the walker's first radius (plain lists start at 0) and past the end.
 template <typename T>
 void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned char* wc_dst, T* thr_dst,
                        double zeta) {
@@ -230,7 +233,10 @@ void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned ch
   c.first = plain ? 0 : wp.first;
   c.partial = wp.partial ? 1 : 0;
   std::memcpy(wc_dst, &c, sizeof c);
-  for (size_t j = 0; j < wp.thr.size(); ++j) thr_dst[j] = static_cast<T>(wp.thr[j]);
+  const T inf = std::numeric_limits<T>::infinity();
+  const int nr = static_cast<int>(wp.thr.size());
+  for (int j = 0; j < xs21::thr_stride(); ++j)
+    thr_dst[j] = (j < c.first || j >= nr) ? inf : static_cast<T>(wp.thr[j]);
 }
 
 // Writes the constants + thresholds of `walkers` for box b into host memory
@@ -242,12 +248,11 @@ void build_tables(const xs21_physics& p, const BoxRec& b, const xs21_walker* w, 
   const int nr = static_cast<int>(radii.size());
   for (int i = 0; i < count; ++i) {
     const auto wp = xs21::plan::walker(p, b.z, radii.data(), nr, w[i]);
+    const size_t ts = static_cast<size_t>(xs21::thr_stride());
     if (b.dtype == xs21::kF64)
-      fill_walker_table<double>(wp, plain, dst + i * wcs, reinterpret_cast<double*>(thr_base) + static_cast<size_t>(i) * nr,
-                                w[i].zeta);
+      fill_walker_table<double>(wp, plain, dst + i * wcs, reinterpret_cast<double*>(thr_base) + i * ts, w[i].zeta);
     else
-      fill_walker_table<float>(wp, plain, dst + i * wcs, reinterpret_cast<float*>(thr_base) + static_cast<size_t>(i) * nr,
-                               w[i].zeta);
+      fill_walker_table<float>(wp, plain, dst + i * wcs, reinterpret_cast<float*>(thr_base) + i * ts, w[i].zeta);
   }
 }
 
@@ -257,7 +262,7 @@ const void* tw_ptr(const xs21_ctx* c, int dtype) {
 
 // Forward 3D real-to-half-complex transform of a real box (in place in `spec`).
 hipError_t forward3d(xs21_ctx* c, const BoxRec& b, const void* real_in, void* spec) {
-  const long n = b.n, h = static_cast<long>(b.half());
+  const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const void* tw = tw_ptr(c, b.dtype);
@@ -266,31 +271,48 @@ hipError_t forward3d(xs21_ctx* c, const BoxRec& b, const void* real_in, void* sp
   });
   if (e != hipSuccess) return e;
   e = timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, n, h, -1, tw, kNtab, c->stream);
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, n, hp, h, -1, tw, kNtab, c->stream);
   });
   if (e != hipSuccess) return e;
   return timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, 1, n * h, -1, tw, kNtab, c->stream);
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, 1, n * hp, n * hp, -1, tw, kNtab, c->stream);
   });
 }
 
-// delta_R = IDFT(mask_R * hat) / N^3 stored as `storage`.
+// delta_R = IDFT(mask_R * hat) / N^3 stored as `storage`.  The three inverse
+// passes only touch the modes the sharp-k ball can hold: the z pass the
+// columns with ny^2 + kx^2 <= n2max, the y pass the columns kx <= kmax, the x
+// pass the entries kx <= kmax of each row; only the delta_R write is full size.
 hipError_t smooth3d(xs21_ctx* c, const BoxRec& b, const void* hat, void* tmp, long n2max, int storage, void* out) {
-  const long n = b.n, h = static_cast<long>(b.half());
+  const long n = b.n, hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
-  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  const double cells = static_cast<double>(b.cells());
   const void* tw = tw_ptr(c, b.dtype);
-  hipError_t e = timed(c, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, +1, hat, tmp, 1, n * h, n2max, tw, kNtab, c->stream);
+  long kmax = static_cast<long>(std::floor(std::sqrt(static_cast<double>(n2max))));
+  while (kmax * kmax > n2max) --kmax;
+  while ((kmax + 1) * (kmax + 1) <= n2max) ++kmax;
+  kmax = std::min(kmax, n / 2);
+  // live (ky, kx) columns of the z pass
+  double live = 0;
+  for (long kx = 0; kx <= kmax; ++kx) {
+    const long r = n2max - kx * kx;
+    long m = static_cast<long>(std::floor(std::sqrt(static_cast<double>(r))));
+    while (m * m > r) --m;
+    while ((m + 1) * (m + 1) <= r) ++m;
+    live += static_cast<double>(std::min(2 * m + 1, n));
+  }
+  hipError_t e = timed(c, XS21_K_AXIS_INV, 2 * live * n * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 1, hat, tmp, 1, n * hp, n * hp, n2max, tw, kNtab, c->stream);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, +1, tmp, tmp, n, h, -1, tw, kNtab, c->stream);
+  e = timed(c, XS21_K_AXIS_INV, (live + (kmax + 1) * n) * n * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 2, tmp, tmp, n, hp, kmax + 1, n2max, tw, kNtab, c->stream);
   });
   if (e != hipSuccess) return e;
   const double scale = 1.0 / (static_cast<double>(n) * n * n);
-  return timed(c, XS21_K_ROWS_C2R, modes * 2 * rs + cells * store_size(storage), [&] {
-    return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, tw, kNtab, c->stream);
+  return timed(c, XS21_K_ROWS_C2R, (kmax + 1) * n * n * 2 * rs + cells * store_size(storage), [&] {
+    return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, static_cast<int>(kmax), tw, kNtab,
+                                 c->stream);
   });
 }
 
@@ -314,11 +336,11 @@ hipError_t smooth_box(xs21_ctx* c, const BoxRec& b) {
 hipError_t eval_group(xs21_ctx* c, const BoxRec& b, unsigned char* scratch, const void* dR, int storage, int nr,
                       const void* wc, const void* thr, int count, double* pk, long pk_stride, int nbins_out,
                       double* xhi, long xhi_stride) {
-  const long n = b.n, h = static_cast<long>(b.half());
+  const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   void* spec = scratch;
-  const long tiles = xs21::axis_tiles(b.n, n * h);
+  const long tiles = xs21::axis_tiles(b.n, n * hp);
   double* part = reinterpret_cast<double*>(scratch + align_up(count * b.spec_bytes()));
   double* xpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) +
                                             align_up(static_cast<size_t>(count) * tiles * b.nbins * 8));
@@ -330,11 +352,11 @@ hipError_t eval_group(xs21_ctx* c, const BoxRec& b, unsigned char* scratch, cons
   });
   if (e != hipSuccess) return e;
   e = timed(c, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, spec, spec, count * n, h, -1, tw, kNtab, c->stream);
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, count * n, hp, h, -1, tw, kNtab, c->stream);
   });
   if (e != hipSuccess) return e;
   e = timed(c, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
-    return xs21::launch_axis_bins(b.dtype, b.n, spec, count, n * h,
+    return xs21::launch_axis_bins(b.dtype, b.n, spec, count, n * hp,
                                   reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, part, tw, kNtab,
                                   c->stream);
   });
@@ -603,7 +625,7 @@ xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
         double* xh_out = xhi_mean ? xhi_mean + wg * nb + i : nullptr;
         HIPCHECK(ctx, eval_group(ctx, b, ctx->ws + ctx->lay.scratch, ctx->ws + b.off_dR, b.storage, b.nr(),
                                  wc + g0 * b.wc_size(),
-                                 thr + static_cast<size_t>(g0) * b.nr() * real_size(b.dtype), g, pk_out,
+                                 thr + static_cast<size_t>(g0) * xs21::thr_stride() * real_size(b.dtype), g, pk_out,
                                  static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
       }
     }
@@ -646,7 +668,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
 
   if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
   build_tables(ctx->phys, b, walker, 1, true, r, static_cast<unsigned char*>(ctx->pinned), 1);
-  const size_t tb_bytes = align_up(b.wc_size()) + align_up(nr * real_size(b.dtype));
+  const size_t tb_bytes = align_up(b.wc_size()) + align_up(xs21::thr_stride() * real_size(b.dtype));
   unsigned char* wc = ctx->ws + ctx->lay.one_table;
   HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
@@ -691,7 +713,7 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   const BoxRec& b = ctx->boxes[box];
   if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
   build_tables(ctx->phys, b, walker, 1, false, b.radii, static_cast<unsigned char*>(ctx->pinned), 1);
-  const size_t tb_bytes = align_up(b.wc_size()) + align_up(b.nr() * real_size(b.dtype));
+  const size_t tb_bytes = align_up(b.wc_size()) + align_up(xs21::thr_stride() * real_size(b.dtype));
   unsigned char* wc = ctx->ws + ctx->lay.one_table;
   HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
@@ -724,14 +746,14 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!field || !pk) return fail(XS21_EINVAL, "null argument");
   const BoxRec& b = ctx->boxes[box];
-  const long n = b.n, h = static_cast<long>(b.half());
+  const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   unsigned char* s = ctx->ws + ctx->lay.scratch;
-  const long tiles = xs21::axis_tiles(b.n, n * h);
+  const long tiles = xs21::axis_tiles(b.n, n * hp);
   double* part = reinterpret_cast<double*>(s + align_up(b.spec_bytes()));
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, s, n * n, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, s, s, n, h, -1, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, n * h, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
+  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, s, s, n, hp, h, -1, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, n * hp, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
                                        b.nbins, part, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;
   HIPCHECK(ctx, xs21::launch_finalize(1, part, tiles, b.nbins, nullptr, 0,

@@ -27,9 +27,15 @@ template <> struct FftPlan<128> { static constexpr int R0 = 16, R1 = 8,  R2 = 1;
 template <> struct FftPlan<256> { static constexpr int R0 = 16, R1 = 16, R2 = 1; };
 template <> struct FftPlan<512> { static constexpr int R0 = 8,  R1 = 8,  R2 = 8; };
 
-template <int N>
+// A radix plan: three stages (radix 1 = unused).
+template <int A, int B, int C>
+struct Radices {
+  static constexpr int R0 = A, R1 = B, R2 = C;
+};
+
+template <int N, typename P = FftPlan<N>>
 struct FftShape {
-  static constexpr int R0 = FftPlan<N>::R0, R1 = FftPlan<N>::R1, R2 = FftPlan<N>::R2;
+  static constexpr int R0 = P::R0, R1 = P::R1, R2 = P::R2;
   static constexpr int RMAX = R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2);
   static constexpr int TS = N / RMAX;  // threads per transform (team size)
   static_assert(R0 * R1 * R2 == N, "radix plan does not multiply to N");
@@ -115,10 +121,9 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* __restrict__ tw, int m
 // One Stockham stage of radix R after spans of length NS are complete.
 // Butterflies b = j, j + TS, ... (N/R of them); results overwrite buf in place,
 // so the stage reads everything into registers, synchronises, then writes.
-template <int N, int R, int NS, int DIR, typename T>
+template <int N, int R, int NS, int DIR, typename T, int TS>
 __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, const cplx<T>* __restrict__ tw,
                                                int tstride) {
-  constexpr int TS = FftShape<N>::TS;
   constexpr int NB = N / R;          // butterflies in this stage
   constexpr int BPT = NB / TS;       // butterflies per thread
   static_assert(NB % TS == 0, "team size must divide the butterfly count");
@@ -150,13 +155,21 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, cons
 // by team member j in [0, TS).  Every thread of the block must call this
 // (it synchronises the block); data must be in LDS and visible on entry.
 // DIR = -1: X[k] = sum_n x[n] exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
-template <int N, int DIR, typename T>
+template <int N, int DIR, typename T, typename Plan = FftPlan<N>>
 __device__ __forceinline__ void fft_team(cplx<T>* buf, int es, int j, const cplx<T>* __restrict__ tw,
                                          int tstride) {
-  using P = FftShape<N>;
-  stockham_stage<N, P::R0, 1, DIR, T>(buf, es, j, tw, tstride);
-  if constexpr (P::R1 > 1) stockham_stage<N, P::R1, P::R0, DIR, T>(buf, es, j, tw, tstride);
-  if constexpr (P::R2 > 1) stockham_stage<N, P::R2, P::R0 * P::R1, DIR, T>(buf, es, j, tw, tstride);
+  using P = FftShape<N, Plan>;
+  stockham_stage<N, P::R0, 1, DIR, T, P::TS>(buf, es, j, tw, tstride);
+  if constexpr (P::R1 > 1) stockham_stage<N, P::R1, P::R0, DIR, T, P::TS>(buf, es, j, tw, tstride);
+  if constexpr (P::R2 > 1) stockham_stage<N, P::R2, P::R0 * P::R1, DIR, T, P::TS>(buf, es, j, tw, tstride);
+}
+
+// Copies the twiddles of a length-N transform into LDS (twl[m] = exp(-2 pi i m / N)).
+// All threads of the block must call it; it synchronises the block.
+template <int N, typename T>
+__device__ __forceinline__ void load_twiddles(cplx<T>* twl, const cplx<T>* __restrict__ tw, int tstride) {
+  for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = tw[m * tstride];
+  __syncthreads();
 }
 
 }  // namespace xs21

@@ -17,18 +17,23 @@ long axis_tiles(int n, long inner);     // blocks along the inner dimension
 int ion_grid(int n);                    // blocks of the ionisation pass
 int max_group();                        // walkers per ionisation launch
 int max_radii();                        // radii per ladder
+int thr_stride();                       // padded thresholds per walker (+inf beyond use)
 int max_bins();                         // bins per spectrum
+int half_pitch(int n);                  // row pitch (complex values) of a half spectrum
 
-// Real rows [nrows][n] of `dtype` -> half-spectrum rows [nrows][n/2+1].
+// Real rows [nrows][n] of `dtype` -> half-spectrum rows [nrows][half_pitch(n)].
 hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nrows, const void* tw, int ntab,
                            hipStream_t s);
-// Half-spectrum rows -> real rows * scale, stored as `storage`.
+// Half-spectrum rows -> real rows * scale, stored as `storage`; entries with
+// kx > kmax are taken as zero without being read.
 hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* out, long nrows, double scale,
-                           const void* tw, int ntab, hipStream_t s);
-// Transform along the middle axis of [outer][n][inner] (dir -1 forward, +1
-// inverse); n2max >= 0 applies the sharp-k mask before an inverse z pass.
-hipError_t launch_axis(int dtype, int n, int dir, const void* src, void* dst, long outer, long inner, long n2max,
-                       const void* tw, int ntab, hipStream_t s);
+                           int kmax, const void* tw, int ntab, hipStream_t s);
+// Transform along the middle axis of [outer][n][inner] for columns < ilim
+// (dir -1 forward, +1 inverse).  mode 0 plain; mode 1 the z pass of a sharp-k
+// smoothing (|n|^2 <= n2max kept, columns outside the disk skipped); mode 2
+// the y pass of a smoothing (only entries with ny^2 + kx^2 <= n2max read).
+hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
+                       long ilim, long n2max, const void* tw, int ntab, hipStream_t s);
 // Forward z pass of [outer][n][n*(n/2+1)] fused with |X|^2 binning into
 // part[outer][axis_tiles][nbins] (FP64).
 hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, long inner, const int8_t* bintab,

@@ -1,0 +1,106 @@
+// Wave64 reductions with DPP (data-parallel primitives) and a fast erfc.
+#pragma once
+
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace xs21 {
+
+// DPP controls (GFX9): quad permutes, row mirrors, row broadcasts.
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane j of each 8 reads 7 - j
+constexpr int kDppRowMirror = 0x140;  // lane j of each 16 reads 15 - j
+constexpr int kDppBcast15 = 0x142;    // lane 15 of row r feeds row r + 1
+constexpr int kDppBcast31 = 0x143;    // lane 31 feeds rows 2 and 3
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+
+// One reduction step: every enabled lane combines its value with a partner
+// lane's; lanes of disabled rows combine with the identity `idb`.
+template <int CTRL, int ROWS, typename Op>
+__device__ __forceinline__ float dpp_step(float v, float id, Op op) {
+  return op(v, __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(id), __float_as_int(v))));
+}
+template <int CTRL, int ROWS, typename Op>
+__device__ __forceinline__ int dpp_step(int v, int id, Op op) {
+  return op(v, dpp_move<CTRL, ROWS>(id, v));
+}
+template <int CTRL, int ROWS, typename Op>
+__device__ __forceinline__ double dpp_step(double v, double id, Op op) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v), ib = __builtin_bit_cast(uint64_t, id);
+  const uint32_t lo = static_cast<uint32_t>(dpp_move<CTRL, ROWS>(static_cast<int>(ib), static_cast<int>(b)));
+  const uint32_t hi =
+      static_cast<uint32_t>(dpp_move<CTRL, ROWS>(static_cast<int>(ib >> 32), static_cast<int>(b >> 32)));
+  return op(v, __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+template <typename T>
+__device__ __forceinline__ T read_lane63(T v);
+template <>
+__device__ __forceinline__ float read_lane63<float>(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <>
+__device__ __forceinline__ int read_lane63<int>(int v) {
+  return __builtin_amdgcn_readlane(v, 63);
+}
+template <>
+__device__ __forceinline__ double read_lane63<double>(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b), 63));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Reduction of v over the 64 lanes of a full wave; the result is returned in
+// every lane (read back from lane 63, so it is wave-uniform).  The combining
+// order is fixed, so results are deterministic.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T id, Op op) {
+  v = dpp_step<kDppQuadSwap1, 0xf>(v, id, op);
+  v = dpp_step<kDppQuadSwap2, 0xf>(v, id, op);
+  v = dpp_step<kDppHalfMirror, 0xf>(v, id, op);
+  v = dpp_step<kDppRowMirror, 0xf>(v, id, op);
+  v = dpp_step<kDppBcast15, 0xa>(v, id, op);
+  v = dpp_step<kDppBcast31, 0xc>(v, id, op);
+  return read_lane63(v);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  return wave_reduce(v, T(0), [](T a, T b) { return a + b; });
+}
+__device__ __forceinline__ int wave_min(int v) {
+  return wave_reduce(v, 0x7fffffff, [](int a, int b) { return a < b ? a : b; });
+}
+__device__ __forceinline__ int wave_max(int v) {
+  return wave_reduce(v, -0x7fffffff - 1, [](int a, int b) { return a > b ? a : b; });
+}
+
+// erfc(x) = t exp(-z^2 + P(t)), t = 1 / (1 + z/2), z = |x|, P a degree-9
+// Chebyshev fit (Press, Teukolsky, Vetterling & Flannery, Numerical Recipes,
+// 2nd ed., section 6.2, "erfcc"): fractional error below 1.2e-7 for all x;
+// erfc(-z) = 2 - erfc(z).
+__device__ __forceinline__ float erfc_fast(float x) {
+  const float z = fabsf(x);
+  const float t = __fdividef(1.0f, 1.0f + 0.5f * z);
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float r = t * __expf(fmaf(-z, z, p));
+  return x >= 0.0f ? r : 2.0f - r;
+}
+
+}  // namespace xs21

@@ -45,6 +45,41 @@ void wave_exchange(const void* in, void* out, size_t bytes, int src_lane) {
   w->bar->arrive_and_wait();
 }
 
+unsigned long long wave_ballot(bool pred) {
+  Wave* w = tl_wave;
+  w->slot[tl_lane][0] = pred ? 1 : 0;
+  w->bar->arrive_and_wait();
+  unsigned long long m = 0;
+  for (int l = 0; l < w->size; ++l)
+    if (w->slot[l][0]) m |= 1ull << l;
+  w->bar->arrive_and_wait();
+  return m;
+}
+
+// DPP move: lane i takes src from a partner lane chosen by ctrl; lanes of rows
+// (16 lanes) or banks (4 lanes within a row) disabled by the masks keep old.
+int wave_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  Wave* w = tl_wave;
+  std::memcpy(w->slot[tl_lane], &src, sizeof(int));
+  w->bar->arrive_and_wait();
+  const int i = tl_lane, row = i / 16, j = i % 16;
+  int sl = -1;
+  if (ctrl >= 0 && ctrl <= 0xff) sl = 4 * (i / 4) + ((ctrl >> (2 * (i % 4))) & 3);
+  else if (ctrl == 0x140) sl = 16 * row + (15 - j);
+  else if (ctrl == 0x141) sl = 16 * row + 8 * (j / 8) + (7 - j % 8);
+  else if (ctrl == 0x142) sl = row > 0 ? 16 * row - 1 : -1;
+  else if (ctrl == 0x143) sl = row > 1 ? 31 : -1;
+  else { std::fprintf(stderr, "emulated DPP control %#x not supported\n", ctrl); std::abort(); }
+  int r = old;
+  const bool enabled = ((row_mask >> row) & 1) && ((bank_mask >> (j / 4)) & 1);
+  if (enabled) {
+    if (sl >= 0 && sl < w->size) std::memcpy(&r, w->slot[sl], sizeof(int));
+    else if (bound_ctrl) r = 0;
+  }
+  w->bar->arrive_and_wait();
+  return r;
+}
+
 void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg) {
   const int nt = static_cast<int>(block.x);
   g_grid = grid;

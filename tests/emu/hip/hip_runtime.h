@@ -54,6 +54,8 @@ extern dim3 g_grid, g_block;
 void syncthreads();
 void wave_exchange(const void* in, void* out, size_t bytes, int src_lane);
 int lane_id();
+unsigned long long wave_ballot(bool pred);
+int wave_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
 void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg);
 hipError_t last_error(hipError_t set = -1);
 }  // namespace hipemu
@@ -72,6 +74,24 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   ::hipemu::wave_exchange(&v, &r, sizeof(T), ::hipemu::lane_id() ^ mask);
   return r;
 }
+
+inline unsigned long long __ballot(int pred) {
+  return ::hipemu::wave_ballot(pred != 0);
+}
+inline unsigned __lane_id() { return static_cast<unsigned>(::hipemu::lane_id()); }
+
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  return ::hipemu::wave_dpp(old, src, ctrl, row_mask, bank_mask, bound_ctrl);
+}
+inline int __builtin_amdgcn_readlane(int v, int lane) {
+  int r;
+  ::hipemu::wave_exchange(&v, &r, sizeof(int), lane);
+  return r;
+}
+inline int __float_as_int(float f) { return __builtin_bit_cast(int, f); }
+inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
+inline float __fdividef(float a, float b) { return a / b; }
+inline float __expf(float x) { return expf(x); }
 
 using std::max;
 using std::min;

@@ -1,0 +1,114 @@
+"""The library's own kernel and host sources, built for the CPU emulation of HIP
+(tests/emu, AddressSanitizer on), against the FP64 oracle.
+
+This is not the GPU path: it checks indexing, synchronisation structure, edge
+cases and host logic of the same source files without a GPU.  The GPU parity
+tests (test_gpu_parity.py) are the parity claim.
+"""
+import numpy as np
+import pytest
+
+import emu_harness as eh
+import oracle
+import synth
+
+AMP = synth.reference_amplitude()
+PHYS = oracle.Physics(pk_amp=AMP)
+EDGE = [(30.0, 15.0, 5e4), (100.0, 20.0, 1e4), (5.0, 5.0, 1e6), (0.4, 12.0, 2e4), (60.0, 1.0, 3e4),
+        (0.8, 9.0, 2e4)]
+
+
+def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True):
+    nbmax = max(s[3] for s in specs)
+    pk = run.read("batch_pk.bin", np.float64, (len(walkers), len(specs), nbmax))
+    xm = run.read("batch_xhi.bin", np.float64, (len(walkers), len(specs)))
+    for bi, (n, box, z, nb) in enumerate(specs):
+        dt = boxes[bi].dtype
+        shared = oracle.shared_radii(n, box, PHYS)
+        for wi, w in enumerate(walkers):
+            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+            ok = ev.counts > 0
+            scale = max(ev.pk[ok].max(), 1e-30)
+            np.testing.assert_allclose(pk[wi, bi, :nb][ok], ev.pk[ok], rtol=tol_pk, atol=tol_pk * scale)
+            assert np.all(pk[wi, bi, nb:] == 0)
+            assert xm[wi, bi] == pytest.approx(ev.xhi_mean, abs=max(tol_pk, 1e-12))
+            if wi == 1:
+                x = run.read(f"mat_b{bi}_w1_xhi.bin", dt, (n, n, n))
+                assert np.mean((x == 0) != ev.flagged) <= flips_max
+        if plain:
+            w = walkers[0]
+            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.plain_radii(w[1], n, box, PHYS), nb, PHYS)
+            x = run.read(f"plain_b{bi}_w0_xhi.bin", dt, (n, n, n))
+            d = run.read(f"plain_b{bi}_w0_dtb.bin", dt, (n, n, n))
+            p = run.read(f"plain_b{bi}_w0_pk.bin", np.float64)[:nb]
+            assert np.mean((x == 0) != ev.flagged) <= flips_max
+            same = (x == 0) == ev.flagged
+            assert np.abs(x.astype(np.float64) - ev.x_hi)[same].max() <= max(tol_pk, 1e-12) * 10
+            assert np.abs(d.astype(np.float64) - ev.dtb)[same].max() <= max(tol_pk, 1e-12) * 300
+            np.testing.assert_allclose(p, ev.pk, rtol=tol_pk)
+            np.testing.assert_array_equal(run.read(f"plain_b{bi}_w0_cnt.bin", np.float64)[:nb], ev.counts)
+
+
+def _run(storage, specs, walkers, max_walkers, dtype, extra=()):
+    run = eh.EmuRun(storage=storage, max_walkers=max_walkers, phys={"pk_amp": AMP})
+    boxes = []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=60 + i, amp=AMP, dtype=dtype)
+        boxes.append(d)
+        run.box(d, box, z, nb)
+    for w in walkers:
+        run.walker(*w)
+    run.cmd("prepare")
+    run.cmd(f"batch {max(s[3] for s in specs)}")
+    for bi in range(len(specs)):
+        run.cmd(f"plain {bi} 0 -")
+        run.cmd(f"materialize {bi} 1")
+    for c in extra:
+        run.cmd(c)
+    run.run()
+    return run, boxes
+
+
+def test_emu_f64_two_geometries_chunked():
+    specs = [(8, 6.0, 9.0, 3), (16, 12.0, 8.0, 4)]   # cell 0.75 Mpc: M_min can exceed the cell mass
+    run, boxes = _run("f64", specs, EDGE, 2, np.float64, extra=("smoothed 1 3", "smoothed 1 0"))
+    _check(run, boxes, specs, EDGE, 1e-11, 0.0)
+    dh = np.fft.rfftn(boxes[1])
+    shared = oracle.shared_radii(16, 12.0, PHYS)
+    for j in (0, 3):
+        got = run.read(f"sm_b1_j{j}.bin", np.float64, (16, 16, 16))
+        np.testing.assert_allclose(got, oracle.smooth(dh, 16, 12.0, shared[j]), atol=1e-13)
+
+
+def test_emu_f32_and_bf16():
+    specs = [(16, 32.0, 9.0, 5)]
+    run, boxes = _run("f32", specs, EDGE[:4], 8, np.float32)
+    _check(run, boxes, specs, EDGE[:4], 2e-5, 1e-3)
+    run, boxes = _run("bf16", specs, EDGE[:4], 8, np.float32)
+    _check(run, boxes, specs, EDGE[:4], 5e-2, 3e-2, plain=False)
+
+
+def test_emu_power_spectrum_plane_wave():
+    n, box, nb, amp = 8, 20.0, 3, 0.9
+    run = eh.EmuRun(storage="f64", max_walkers=1, phys={"pk_amp": AMP})
+    run.box(np.zeros((n, n, n)), box, 9.0, nb)
+    g = np.indices((n, n, n))
+    m = (1, 1, 2)
+    f = amp * np.cos(2 * np.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n)
+    path = run.write_array("field.bin", f)
+    run.cmd("prepare")
+    run.cmd(f"pk 0 {path}")
+    run.run()
+    pk = run.read("fpk_b0.bin", np.float64)[:nb]
+    _, _, counts, _ = oracle.power_spectrum(f, box, nb)
+    b = oracle.bin_of_n2(6, n, nb)
+    expect = np.zeros(nb)
+    expect[b] = amp ** 2 * box ** 3 / (2 * counts[b])
+    np.testing.assert_allclose(pk, expect, rtol=1e-12, atol=1e-12 * expect.max())
+
+
+def test_emu_rejects_bad_box():
+    run = eh.EmuRun(storage="f32", max_walkers=1, phys={"pk_amp": AMP})
+    run.box(np.zeros((12, 12, 12), dtype=np.float32), 10.0, 9.0, 3)
+    with pytest.raises(RuntimeError, match="power of two"):
+        run.run()
