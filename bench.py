@@ -14,6 +14,7 @@ algorithmic bytes), and the FP64 CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,35 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# Vector ALU issue peak without packed FP32 (disabled in this build): 256 CUs x
+# 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations per second.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device sources; traffic figures are only reused for the same code."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1501_06576_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None if
+    the kernels changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def log(msg):
@@ -41,6 +71,9 @@ def main():
     ap.add_argument("--workload", default="batched-256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-walkers", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-walker form")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by walkers and "
@@ -110,24 +143,30 @@ def main():
             cellR += float(s.n) ** 3 * (np.count_nonzero(shared[:-1] <= w[1]) + 1)
 
     # plain per-walker GPU form
-    log("timing plain per-walker form")
-    pw = walkers[: args.plain_walkers]
-    for h in hs:
-        ctx.eval(h, pw[0], fields=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for w in pw:
+    ms_plain = None
+    if not args.no_plain and args.plain_walkers > 0:
+        log("timing plain per-walker form")
+        pw = walkers[: args.plain_walkers]
         for h in hs:
-            ctx.eval(h, w, fields=False)
-    torch.cuda.synchronize()
-    ms_plain = (time.perf_counter() - t0) * 1e3 / len(pw)
+            ctx.eval(h, pw[0], fields=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w in pw:
+            for h in hs:
+                ctx.eval(h, w, fields=False)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) * 1e3 / len(pw)
 
-    # roofline of the dominant kernel class over the timed steps
+    # roofline of the dominant kernel class over the timed steps: the bound is
+    # whichever of HBM bytes and vector ALU operations is closer to its peak
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
     bytes_launch = d["bytes"] / max(d["launches"], 1)
+    ops_launch = d["ops"] / max(d["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    achieved_ops = ops_launch / (avg_ms * 1e-3) / 1e12
+    alu_bound = achieved_ops / VALU_PEAK_TOPS > achieved / HBM_PEAK_GBS
     kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
                    "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items() if v["launches"]}
 
@@ -150,11 +189,18 @@ def main():
         "gcell_r_per_s": round(cellR / (ms_step * 1e-3) / 1e9, 2),
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
                          "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2)},
-        "plain_per_walker": {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
+        "plain_per_walker": None if ms_plain is None else
+        {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
         "kernels": kernels,
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_launch},
+        "roofline": ({"kernel": dom, "bound": "alu", "achieved": round(achieved_ops, 3),
+                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4),
+                      "algorithmic_ops_per_launch": ops_launch, "hbm": {"achieved": round(achieved, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+                     if alu_bound else
+                     {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}) | {
+                     "traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": bytes_launch, "source_hash": kernel_source_hash()},
     }
 
     if not args.no_cpu_baseline:
@@ -172,6 +218,13 @@ def main():
                                   "sample": f"1 walker x 1 box ({s.n}^3, z={s.z}, {len(radii)} radii) in {dt:.2f} s; "
                                             f"a walker eval is {len(hs)} boxes"}
     ctx.close()
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy of 1 GiB done")
     print(json.dumps(result), flush=True)
 
 

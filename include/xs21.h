@@ -227,10 +227,15 @@ typedef enum {
 xs21_status xs21_profile(xs21_ctx* ctx, int enable);
 
 /* Synchronises the context stream, then returns for kernel class `kind` the
- * summed duration (ms), the number of launches, and the summed algorithmic
- * bytes (the compulsory HBM reads + writes of each launch's inputs and
- * outputs).  Any output pointer may be NULL. */
-xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes);
+ * summed duration (ms), the number of launches, the summed algorithmic bytes
+ * (the compulsory HBM reads + writes of each launch's inputs and outputs) and
+ * the summed algorithmic vector operations of the per-cell pass
+ * (XS21_K_ION only, else 0): per walker-cell one compare per radius the
+ * walker filters at, 2.5 log2(N) for its share of the x-axis FFT and 6 for
+ * the brightness temperature, packing and unpacking.  Any output pointer may
+ * be NULL. */
+xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes,
+                              double* ops);
 
 /* ---------------------------------------------------------------- host planning */
 /* Pure host functions (no device, no context): the FP64 scalar planning the

@@ -66,7 +66,7 @@ _SIGNATURES = {
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
     "xs21_resmooth": (_I, [_P, _I, _P]),
     "xs21_profile": (_I, [_P, _I]),
-    "xs21_profile_read": (_I, [_P, _I, _DP, ctypes.POINTER(ctypes.c_longlong), _DP]),
+    "xs21_profile_read": (_I, [_P, _I, _DP, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
     "xs21_plan_ladder": (_I, [_D, _D, _D, _DP, _I, _IP]),
     "xs21_plan_sigma2": (_I, [ctypes.POINTER(Physics), _D, _D, _DP]),
     "xs21_plan_walker": (_I, [ctypes.POINTER(Physics), _D, _DP, _I, ctypes.POINTER(Walker), _DP, _DP, _IP, _DP]),
@@ -304,14 +304,16 @@ class Context:
         _check(library().xs21_profile(self._ctx, 1 if enable else 0))
 
     def profile_read(self) -> dict:
-        """Per kernel class: total ms, launches and algorithmic bytes since profile(True)."""
+        """Per kernel class: total ms, launches, algorithmic bytes and vector ops since profile(True)."""
         out = {}
         for k, name in enumerate(KERNELS):
             ms = ctypes.c_double()
             n = ctypes.c_longlong()
             by = ctypes.c_double()
-            _check(library().xs21_profile_read(self._ctx, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
-            out[name] = {"ms": ms.value, "launches": n.value, "bytes": by.value}
+            op = ctypes.c_double()
+            _check(library().xs21_profile_read(self._ctx, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+                                               ctypes.byref(op)))
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": by.value, "ops": op.value}
         return out
 
     def sync(self):

@@ -1,9 +1,11 @@
 // C-ABI of the xs21 library: context, boxes, workspace layout, prepare and
-// evaluation drivers.  All device memory is the caller's workspace.
+// evaluation drivers.  All device memory is the caller's workspace; all device
+// work is issued in order to the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -54,8 +56,10 @@ struct BoxRec {
   std::vector<int8_t> bintab;
   std::vector<double> counts, kmean;
   int storage = 0;
+  int rbatch = 1;             // radii smoothed per launch
+  std::vector<long> cut;      // (n2max, kmax) per ladder radius
   // workspace offsets
-  size_t off_bintab = 0, off_counts = 0, off_delta = 0, off_dR = 0;
+  size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_dR = 0;
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
   size_t half() const { return static_cast<size_t>(n / 2 + 1); }
@@ -73,7 +77,7 @@ struct Layout {
   size_t tables = 0, tables_bytes = 0;     // batched walker tables (all boxes)
   size_t one_table = 0, one_table_bytes = 0;  // single-walker table
   size_t outs = 0;                          // small device outputs (plain / debug)
-  size_t scratch = 0, scratch_bytes = 0;    // union of prepare / eval / plain scratch
+  size_t scratch = 0, scratch_bytes = 0;    // union of smoothing / evaluation / plain scratch
   size_t total = 0;
 };
 
@@ -101,7 +105,7 @@ struct xs21_ctx {
   struct ProfRec {
     int kind;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, ops;
   };
   bool prof = false;
   std::vector<ProfRec> pending;
@@ -109,6 +113,7 @@ struct xs21_ctx {
   double tot_ms[XS21_K_COUNT] = {};
   long long launches[XS21_K_COUNT] = {};
   double tot_bytes[XS21_K_COUNT] = {};
+  double tot_ops[XS21_K_COUNT] = {};
 };
 
 namespace {
@@ -148,32 +153,58 @@ hipEvent_t pooled_event(xs21_ctx* c) {
   return e;
 }
 
-// Launches through `f`; when timing is on, brackets it with events on the
-// context stream and remembers the pair with the launch's algorithmic bytes.
+// Launches through `f` on stream s; when timing is on, brackets it with events
+// on s and remembers the pair with the launch's algorithmic bytes and ops.
 template <typename F>
-hipError_t timed(xs21_ctx* c, int kind, double bytes, F&& f) {
+hipError_t timed(xs21_ctx* c, hipStream_t s, int kind, double bytes, F&& f, double ops = 0.0) {
   if (!c->prof) return f();
   hipEvent_t a = pooled_event(c), b = pooled_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, c->stream);
+  hipError_t e = hipEventRecord(a, s);
   if (e != hipSuccess) return e;
   e = f();
   if (e != hipSuccess) return e;
-  e = hipEventRecord(b, c->stream);
+  e = hipEventRecord(b, s);
   if (e != hipSuccess) return e;
-  c->pending.push_back({kind, a, b, bytes});
+  c->pending.push_back({kind, a, b, bytes, ops});
   return hipSuccess;
 }
 
+
 bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+long isqrt(long v) {
+  long r = static_cast<long>(std::floor(std::sqrt(static_cast<double>(v))));
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+// (n2max, kmax) of a sharp-k smoothing of radius R on box b: kmax is the
+// largest |kx| any kept mode can have.
+void cut_pair(const BoxRec& b, double radius, long* out) {
+  const long n2 = xs21::plan::n2max(radius, b.box);
+  out[0] = n2;
+  out[1] = std::min(isqrt(n2), static_cast<long>(b.n / 2));
+}
+
+// Radii smoothed per launch: as many as fit a 4 GiB batch of spectra (the
+// environment variable XS21_RADIUS_BATCH overrides it).
+int radius_batch(const BoxRec& b) {
+  long rb = static_cast<long>((4ull << 30) / b.spec_bytes());
+  if (const char* e = std::getenv("XS21_RADIUS_BATCH")) rb = std::atol(e);
+  return static_cast<int>(std::max(1L, std::min<long>(rb, b.nr())));
+}
 
 int box_storage(const BoxRec& b, int storage) { return b.dtype == xs21::kF64 ? xs21::kF64 : storage; }
 
-// Scratch needed by each phase, per box; the scratch region is their maximum.
-size_t prepare_scratch(const BoxRec& b) { return 2 * align_up(b.spec_bytes()); }
+// Scratch of each phase, per box; each region is the maximum over boxes.
+// Smoothing: the box spectrum + one spectrum per radius of a launch batch.
+size_t smooth_scratch(const BoxRec& b) { return (1 + static_cast<size_t>(b.rbatch)) * align_up(b.spec_bytes()); }
 
+// Evaluation: walker spectra, bin partial sums, x_HI partial sums.
 size_t eval_scratch(const BoxRec& b, int group) {
-  const long tiles = xs21::axis_tiles(b.n, static_cast<long>(b.n) * b.pitch());
+  const long tiles = xs21::bins_tiles(b.n);
   return align_up(group * b.spec_bytes()) + align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
          align_up(static_cast<size_t>(group) * xs21::ion_grid(b.n) * 8);
 }
@@ -194,17 +225,21 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
   size_t tables = 0, one = 0, scratch = 0;
   for (auto& b : boxes) {
     b.storage = box_storage(b, storage);
+    b.rbatch = radius_batch(b);
     b.off_bintab = off;
     off += align_up(b.bintab.size());
     b.off_counts = off;
     off += align_up(b.nbins * 8);
+    b.off_cut = off;
+    off += align_up(b.cut.size() * sizeof(long));
     b.off_delta = off;
     off += align_up(b.cells() * real_size(b.dtype));
     b.off_dR = off;
     off += align_up(static_cast<size_t>(b.nr()) * b.cells() * store_size(b.storage));
     tables += b.table_bytes(max_walkers);
-    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(xs21::thr_stride() * 8));
-    scratch = std::max({scratch, prepare_scratch(b), eval_scratch(b, group), plain_scratch(b, max_plain)});
+    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(xs21::thr_stride() * 8) +
+                            align_up(2 * sizeof(long) * xs21::max_radii()));
+    scratch = std::max({scratch, smooth_scratch(b), eval_scratch(b, group), plain_scratch(b, max_plain)});
   }
   (void)c;
   L.tables = off;
@@ -260,114 +295,148 @@ const void* tw_ptr(const xs21_ctx* c, int dtype) {
   return c->ws + (dtype == xs21::kF64 ? c->lay.tw64 : c->lay.tw32);
 }
 
-// Forward 3D real-to-half-complex transform of a real box (in place in `spec`).
-hipError_t forward3d(xs21_ctx* c, const BoxRec& b, const void* real_in, void* spec) {
+// Forward 3D real-to-half-complex transform of a real box (in place in `spec`), on stream st.
+hipError_t forward3d(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* real_in, void* spec) {
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const void* tw = tw_ptr(c, b.dtype);
-  hipError_t e = timed(c, XS21_K_ROWS_R2C, cells * rs + modes * 2 * rs, [&] {
-    return xs21::launch_rows_r2c(b.dtype, b.n, real_in, spec, n * n, tw, kNtab, c->stream);
+  hipError_t e = timed(c, st, XS21_K_ROWS_R2C, cells * rs + modes * 2 * rs, [&] {
+    return xs21::launch_rows_r2c(b.dtype, b.n, real_in, spec, n * n, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, n, hp, h, -1, tw, kNtab, c->stream);
+  e = timed(c, st, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, n, hp, h, nullptr, 1, 0, 0, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
-  return timed(c, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, 1, n * hp, n * hp, -1, tw, kNtab, c->stream);
+  return timed(c, st, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, 1, n * hp, n * hp, nullptr, 1, 0, 0, tw, kNtab, st);
   });
 }
 
-// delta_R = IDFT(mask_R * hat) / N^3 stored as `storage`.  The three inverse
-// passes only touch the modes the sharp-k ball can hold: the z pass the
-// columns with ny^2 + kx^2 <= n2max, the y pass the columns kx <= kmax, the x
-// pass the entries kx <= kmax of each row; only the delta_R write is full size.
-hipError_t smooth3d(xs21_ctx* c, const BoxRec& b, const void* hat, void* tmp, long n2max, int storage, void* out) {
+// delta_R = IDFT(mask_R * hat) / N^3 stored as `storage` for `cnt` radii at
+// once: radius i uses cutoff pair cut_dev[2 i], cut_dev[2 i + 1] (device) and
+// cut_host likewise, its own spectrum tmp + i * spec and output out + i * N^3.
+// The three inverse passes only touch the modes the sharp-k ball can hold:
+// the z pass the columns with ny^2 + kx^2 <= n2max, the y pass the columns
+// kx <= kmax, the x pass the entries kx <= kmax of each row; only the delta_R
+// write is full size.
+hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* hat, unsigned char* tmp,
+                        const long* cut_dev, const long* cut_host, int cnt, int storage, unsigned char* out) {
   const long n = b.n, hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells());
   const void* tw = tw_ptr(c, b.dtype);
-  long kmax = static_cast<long>(std::floor(std::sqrt(static_cast<double>(n2max))));
-  while (kmax * kmax > n2max) --kmax;
-  while ((kmax + 1) * (kmax + 1) <= n2max) ++kmax;
-  kmax = std::min(kmax, n / 2);
-  // live (ky, kx) columns of the z pass
-  double live = 0;
-  for (long kx = 0; kx <= kmax; ++kx) {
-    const long r = n2max - kx * kx;
-    long m = static_cast<long>(std::floor(std::sqrt(static_cast<double>(r))));
-    while (m * m > r) --m;
-    while ((m + 1) * (m + 1) <= r) ++m;
-    live += static_cast<double>(std::min(2 * m + 1, n));
+  const long sstride = static_cast<long>(align_up(b.spec_bytes()) / (2 * real_size(b.dtype)));  // complex elements
+  double zb = 0, yb = 0, xb = 0;
+  long kmax_all = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const long n2max = cut_host[2 * i], kmax = cut_host[2 * i + 1];
+    kmax_all = std::max(kmax_all, kmax);
+    double live = 0;  // (ky, kx) columns inside the disk
+    for (long kx = 0; kx <= kmax; ++kx) live += static_cast<double>(std::min(2 * isqrt(n2max - kx * kx) + 1, n));
+    zb += 2 * live * n * 2 * rs;
+    yb += (live + (kmax + 1) * n) * n * 2 * rs;
+    xb += (kmax + 1) * n * n * 2 * rs + cells * store_size(storage);
   }
-  hipError_t e = timed(c, XS21_K_AXIS_INV, 2 * live * n * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, +1, 1, hat, tmp, 1, n * hp, n * hp, n2max, tw, kNtab, c->stream);
+  hipError_t e = timed(c, st, XS21_K_AXIS_INV, zb, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 1, hat, tmp, 1, n * hp, n * hp, cut_dev, cnt, 0, sstride, tw, kNtab,
+                             st);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, XS21_K_AXIS_INV, (live + (kmax + 1) * n) * n * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, +1, 2, tmp, tmp, n, hp, kmax + 1, n2max, tw, kNtab, c->stream);
+  e = timed(c, st, XS21_K_AXIS_INV, yb, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 2, tmp, tmp, n, hp, kmax_all + 1, cut_dev, cnt, sstride, sstride, tw,
+                             kNtab, st);
   });
   if (e != hipSuccess) return e;
   const double scale = 1.0 / (static_cast<double>(n) * n * n);
-  return timed(c, XS21_K_ROWS_C2R, (kmax + 1) * n * n * 2 * rs + cells * store_size(storage), [&] {
-    return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, static_cast<int>(kmax), tw, kNtab,
-                                 c->stream);
+  return timed(c, st, XS21_K_ROWS_C2R, xb, [&] {
+    return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, cut_dev, cnt, sstride,
+                                 static_cast<long>(b.cells()), tw, kNtab, st);
   });
 }
 
-// Forward FFT and every smoothed box of the shared ladder of one box.
-hipError_t smooth_box(xs21_ctx* c, const BoxRec& b) {
+// Forward FFT and every smoothed box of the shared ladder of one box, on stream st.
+hipError_t smooth_box(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
   unsigned char* hat = c->ws + c->lay.scratch;
   unsigned char* tmp = hat + align_up(b.spec_bytes());
-  hipError_t e = forward3d(c, b, c->ws + b.off_delta, hat);
+  hipError_t e = forward3d(c, st, b, c->ws + b.off_delta, hat);
   if (e != hipSuccess) return e;
-  for (int j = 0; j < b.nr(); ++j) {
-    void* out = c->ws + b.off_dR + static_cast<size_t>(j) * b.cells() * store_size(b.storage);
-    e = smooth3d(c, b, hat, tmp, b.n2max[j], b.storage, out);
+  const long* cut_dev = reinterpret_cast<const long*>(c->ws + b.off_cut);
+  for (int j = 0; j < b.nr(); j += b.rbatch) {
+    const int cnt = std::min(b.rbatch, b.nr() - j);
+    unsigned char* out = c->ws + b.off_dR + static_cast<size_t>(j) * b.cells() * store_size(b.storage);
+    e = smooth_batch(c, st, b, hat, tmp, cut_dev + 2 * j, b.cut.data() + 2 * j, cnt, b.storage, out);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// Ionisation + dT_b + P(k) bins for `count` walkers whose tables are at
-// wc/thr, writing pk/xhi (device) with the given strides.  `scratch` is the
-// base of the spectra / partial-sum area.
-hipError_t eval_group(xs21_ctx* c, const BoxRec& b, unsigned char* scratch, const void* dR, int storage, int nr,
-                      const void* wc, const void* thr, int count, double* pk, long pk_stride, int nbins_out,
-                      double* xhi, long xhi_stride) {
+// Scratch of one evaluation of `count` walkers on one box: their x-transformed
+// spectra, then the binning pass's FP64 partial sums, then the ionisation
+// pass's x_HI partial sums.
+struct EvalSlot {
+  void* spec;
+  double* part;
+  double* xpart;
+};
+
+EvalSlot eval_slot(const BoxRec& b, unsigned char* base, int count) {
+  EvalSlot s;
+  s.spec = base;
+  s.part = reinterpret_cast<double*>(base + align_up(count * b.spec_bytes()));
+  s.xpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(s.part) +
+                                      align_up(static_cast<size_t>(count) * xs21::bins_tiles(b.n) * b.nbins * 8));
+  return s;
+}
+
+// Ionisation + dT_b + x pass for `count` walkers whose tables are at wc/thr
+// (the ALU-bound stage), on stream st.
+hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlot& sl, const void* dR, int storage,
+                     int nr, const void* wc, const void* thr, int count, double radii_used) {
+  const long n = b.n, h = static_cast<long>(b.half());
+  const double rs = static_cast<double>(real_size(b.dtype));
+  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  const double tb = c->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+  // radii_used: sum over the group's walkers of the radii each filters at
+  const double ion_ops = cells * (radii_used + count * (2.5 * std::log2(static_cast<double>(n)) + 6.0));
+  return timed(
+      c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
+      [&] {
+        return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_delta, nr, wc, thr, count, tb,
+                                c->phys.delta_c, sl.spec, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
+      },
+      ion_ops);
+}
+
+// y pass, z pass + |X|^2 bins and the final P(k) / mean x_HI of `count`
+// walkers (the memory-bound stage), on stream st; pk/xhi are device outputs
+// written with the given strides.
+hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlot& sl, int count, double* pk,
+                     long pk_stride, int nbins_out, double* xhi, long xhi_stride) {
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
-  void* spec = scratch;
-  const long tiles = xs21::axis_tiles(b.n, n * hp);
-  double* part = reinterpret_cast<double*>(scratch + align_up(count * b.spec_bytes()));
-  double* xpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(part) +
-                                            align_up(static_cast<size_t>(count) * tiles * b.nbins * 8));
-  const double tb = c->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+  const long tiles = xs21::bins_tiles(b.n);
   const void* tw = tw_ptr(c, b.dtype);
-  hipError_t e = timed(c, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs, [&] {
-    return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_delta, nr, wc, thr, count, tb,
-                            c->phys.delta_c, spec, xpart, tw, kNtab, c->stream);
+  hipError_t e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, count * n, hp, h, nullptr, 1, 0, 0, tw, kNtab,
+                             st);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, spec, spec, count * n, hp, h, -1, tw, kNtab, c->stream);
-  });
-  if (e != hipSuccess) return e;
-  e = timed(c, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
-    return xs21::launch_axis_bins(b.dtype, b.n, spec, count, n * hp,
-                                  reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, part, tw, kNtab,
-                                  c->stream);
+  e = timed(c, st, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
+    return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, count,
+                                  reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, sl.part, tw, kNtab,
+                                  st);
   });
   if (e != hipSuccess) return e;
   const double L3 = b.box * b.box * b.box;
   const double n6 = std::pow(static_cast<double>(n), 6);
   const double pbytes = static_cast<double>(count) * (tiles * b.nbins + xs21::ion_grid(b.n)) * 8;
-  return timed(c, XS21_K_FINALIZE, pbytes, [&] {
-    return xs21::launch_finalize(count, part, tiles, b.nbins, xpart, xs21::ion_grid(b.n),
-                                 reinterpret_cast<const double*>(c->ws + b.off_counts), L3 / n6,
-                                 1.0 / cells, pk, pk_stride, nbins_out, xhi, xhi_stride, c->stream);
+  return timed(c, st, XS21_K_FINALIZE, pbytes, [&] {
+    return xs21::launch_finalize(count, sl.part, tiles, b.nbins, sl.xpart, xs21::ion_grid(b.n),
+                                 reinterpret_cast<const double*>(c->ws + b.off_counts), L3 / n6, 1.0 / cells, pk,
+                                 pk_stride, nbins_out, xhi, xhi_stride, st);
   });
 }
 
@@ -468,6 +537,8 @@ xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_d
   if (b.nr() > xs21::max_radii())
     return fail(XS21_EUNSUPPORTED, "ladder of %d radii exceeds %d", b.nr(), xs21::max_radii());
   for (double r : b.radii) b.n2max.push_back(xs21::plan::n2max(r, box_mpc));
+  b.cut.resize(2 * b.radii.size());
+  for (size_t j = 0; j < b.radii.size(); ++j) cut_pair(b, b.radii[j], &b.cut[2 * j]);
   b.bintab = xs21::plan::bins(n, n_bins);
   xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
   if (on_device) {
@@ -563,12 +634,14 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
   for (auto& b : ctx->boxes) {
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_bintab, b.bintab.data(), b.bintab.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_counts, b.counts.data(), b.nbins * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_cut, b.cut.data(), b.cut.size() * sizeof(long), hipMemcpyHostToDevice,
+                                 ctx->stream));
     const size_t dbytes = b.cells() * real_size(b.dtype);
     if (b.dev_src)
       HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.dev_src, dbytes, hipMemcpyDeviceToDevice, ctx->stream));
     else
       HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.host.data(), dbytes, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHECK(ctx, smooth_box(ctx, b));
+    HIPCHECK(ctx, smooth_box(ctx, ctx->stream, b));
   }
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& b : ctx->boxes) {
@@ -598,6 +671,7 @@ xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
   for (int w = 0; w < nw; ++w)
     if (!xs21::plan::valid_walker(walkers[w])) return fail(XS21_EINVAL, "walker %d has invalid parameters", w);
 
+  const hipStream_t st = ctx->stream;
   for (int w0 = 0; w0 < nw; w0 += ctx->max_walkers) {
     const int cnt = std::min(ctx->max_walkers, nw - w0);
     if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
@@ -621,12 +695,22 @@ xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
       for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
         const int g = std::min(ctx->group, cnt - g0);
         const long wg = w0 + g0;
+        double used = 0;
+        for (int k = 0; k < g; ++k) {
+          int first = b.nr() - 1;
+          for (int j = 0; j < b.nr() - 1; ++j)
+            if (b.radii[j] <= walkers[wg + k].r_mfp) {
+              first = j;
+              break;
+            }
+          used += b.nr() - first;
+        }
         double* pk_out = pk ? pk + (wg * nb + i) * nbmax : nullptr;
         double* xh_out = xhi_mean ? xhi_mean + wg * nb + i : nullptr;
-        HIPCHECK(ctx, eval_group(ctx, b, ctx->ws + ctx->lay.scratch, ctx->ws + b.off_dR, b.storage, b.nr(),
-                                 wc + g0 * b.wc_size(),
-                                 thr + static_cast<size_t>(g0) * xs21::thr_stride() * real_size(b.dtype), g, pk_out,
-                                 static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
+        const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, g);
+        HIPCHECK(ctx, ion_stage(ctx, st, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc + g0 * b.wc_size(),
+                                thr + static_cast<size_t>(g0) * xs21::thr_stride() * real_size(b.dtype), g, used));
+        HIPCHECK(ctx, mem_stage(ctx, st, b, sl, g, pk_out, static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
       }
     }
   }
@@ -661,23 +745,30 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
   unsigned char* tmp = hat + align_up(b.spec_bytes());
   unsigned char* dR = tmp + align_up(b.spec_bytes());
   unsigned char* eval_area = dR + align_up(static_cast<size_t>(ctx->max_plain) * b.cells() * real_size(b.dtype));
-  HIPCHECK(ctx, forward3d(ctx, b, ctx->ws + b.off_delta, hat));
-  for (int j = 0; j < nr; ++j)
-    HIPCHECK(ctx, smooth3d(ctx, b, hat, tmp, xs21::plan::n2max(r[j], b.box), b.dtype,
-                           dR + static_cast<size_t>(j) * b.cells() * real_size(b.dtype)));
-
+  // walker table and the radius cutoffs travel in one upload
   if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
-  build_tables(ctx->phys, b, walker, 1, true, r, static_cast<unsigned char*>(ctx->pinned), 1);
+  unsigned char* pin = static_cast<unsigned char*>(ctx->pinned);
+  build_tables(ctx->phys, b, walker, 1, true, r, pin, 1);
   const size_t tb_bytes = align_up(b.wc_size()) + align_up(xs21::thr_stride() * real_size(b.dtype));
+  std::vector<long> cut(2 * nr);
+  for (int j = 0; j < nr; ++j) cut_pair(b, r[j], &cut[2 * j]);
+  std::memcpy(pin + tb_bytes, cut.data(), cut.size() * sizeof(long));
   unsigned char* wc = ctx->ws + ctx->lay.one_table;
-  HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipMemcpyAsync(wc, pin, tb_bytes + cut.size() * sizeof(long), hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   ctx->upload_pending = true;
+  const long* cut_dev = reinterpret_cast<const long*>(wc + tb_bytes);
+  HIPCHECK(ctx, forward3d(ctx, ctx->stream, b, ctx->ws + b.off_delta, hat));
+  for (int j = 0; j < nr; ++j)
+    HIPCHECK(ctx, smooth_batch(ctx, ctx->stream, b, hat, tmp, cut_dev + 2 * j, cut.data() + 2 * j, 1, b.dtype,
+                               dR + static_cast<size_t>(j) * b.cells() * real_size(b.dtype)));
   const unsigned char* thr = wc + align_up(b.wc_size());
 
   // the eval scratch of a plain call sits after the plain smoothed boxes
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
-  HIPCHECK(ctx, eval_group(ctx, b, eval_area, dR, b.dtype, nr, wc, thr, 1, outs, b.nbins, b.nbins, outs + 128, 1));
+  const EvalSlot sl = eval_slot(b, eval_area, 1);
+  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, dR, b.dtype, nr, wc, thr, 1, nr));
+  HIPCHECK(ctx, mem_stage(ctx, ctx->stream, b, sl, 1, outs, b.nbins, b.nbins, outs + 128, 1));
   if (x_hi || dtb) {
     // fields through the same per-cell arithmetic; staged in the hat/tmp area
     const size_t fbytes = b.cells() * real_size(b.dtype);
@@ -686,7 +777,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
     void* fx = hat;
     void* fd = hat + align_up(fbytes);
     const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
-    HIPCHECK(ctx, timed(ctx, XS21_K_OTHER, 0.0, [&] {
+    HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
       return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_delta, nr, wc, thr, tbv,
                                       ctx->phys.delta_c, fx, fd, ctx->stream);
     }));
@@ -719,7 +810,7 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   ctx->upload_pending = true;
   const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
-  HIPCHECK(ctx, timed(ctx, XS21_K_OTHER, 0.0, [&] {
+  HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
     return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_delta, b.nr(), wc,
                                     wc + align_up(b.wc_size()), tbv, ctx->phys.delta_c, x_hi, dtb, ctx->stream);
   }));
@@ -748,12 +839,13 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   const BoxRec& b = ctx->boxes[box];
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   unsigned char* s = ctx->ws + ctx->lay.scratch;
-  const long tiles = xs21::axis_tiles(b.n, n * hp);
+  const long tiles = xs21::bins_tiles(b.n);
   double* part = reinterpret_cast<double*>(s + align_up(b.spec_bytes()));
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, s, n * n, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, s, s, n, hp, h, -1, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, n * hp, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
+  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, s, s, n, hp, h, nullptr, 1, 0, 0, tw_ptr(ctx, b.dtype), kNtab,
+                                  ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
                                        b.nbins, part, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;
   HIPCHECK(ctx, xs21::launch_finalize(1, part, tiles, b.nbins, nullptr, 0,
@@ -774,7 +866,7 @@ xs21_status xs21_resmooth(xs21_ctx* ctx, xs21_box box, const void* new_delta) {
   if (new_delta)
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, new_delta, b.cells() * real_size(b.dtype),
                                  hipMemcpyDeviceToDevice, ctx->stream));
-  HIPCHECK(ctx, smooth_box(ctx, b));
+  HIPCHECK(ctx, smooth_box(ctx, ctx->stream, b));
   return XS21_OK;
 }
 
@@ -788,13 +880,15 @@ xs21_status xs21_profile(xs21_ctx* ctx, int enable) {
       ctx->pool.push_back(r.b);
     }
     ctx->pending.clear();
-    for (int k = 0; k < XS21_K_COUNT; ++k) ctx->tot_ms[k] = ctx->tot_bytes[k] = 0.0, ctx->launches[k] = 0;
+    for (int k = 0; k < XS21_K_COUNT; ++k)
+      ctx->tot_ms[k] = ctx->tot_bytes[k] = ctx->tot_ops[k] = 0.0, ctx->launches[k] = 0;
   }
   ctx->prof = enable != 0;
   return XS21_OK;
 }
 
-xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes) {
+xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes,
+                              double* ops) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
   if (kind < 0 || kind >= XS21_K_COUNT) return fail(XS21_EINVAL, "unknown kernel class %d", kind);
@@ -805,6 +899,7 @@ xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long lo
     ctx->tot_ms[r.kind] += ms;
     ctx->launches[r.kind] += 1;
     ctx->tot_bytes[r.kind] += r.bytes;
+    ctx->tot_ops[r.kind] += r.ops;
     ctx->pool.push_back(r.a);
     ctx->pool.push_back(r.b);
   }
@@ -812,6 +907,7 @@ xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long lo
   if (total_ms) *total_ms = ctx->tot_ms[kind];
   if (launches) *launches = ctx->launches[kind];
   if (bytes) *bytes = ctx->tot_bytes[kind];
+  if (ops) *ops = ctx->tot_ops[kind];
   return XS21_OK;
 }
 

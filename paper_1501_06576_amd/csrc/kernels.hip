@@ -46,9 +46,23 @@ struct RowShape {
   static constexpr int HP = Half<N>::HP;
 };
 
+// Radix plan of the strided passes (y and z axes).  At N = 256 three stages
+// with 32-thread teams (512-thread blocks, 8 values per thread) keep more
+// waves in flight per CU than two radix-16 stages (measured on the 256^3
+// workload).
+template <int N>
+struct AxisPlan {
+  using type = FftPlan<N>;
+};
+template <>
+struct AxisPlan<256> {
+  using type = Radices<8, 8, 4>;
+};
+
 template <int N>
 struct AxisShape {
-  static constexpr int TS = FftShape<N>::TS;
+  using Plan = typename AxisPlan<N>::type;
+  static constexpr int TS = FftShape<N, Plan>::TS;
   static constexpr int TI = (TS == 1) ? 64 : (N <= 128 ? 32 : 16);  // columns per tile
   static constexpr int NT = TI * TS;
 };
@@ -69,28 +83,6 @@ __device__ __forceinline__ void unpack_pair(const cplx<T>* z, int k, cplx<T>& A,
   const T h = T(0.5);
   A = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
   B = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
-}
-
-// Z[k] = A[k] + i B[k] over the full length from the half spectra of two real
-// rows (Hermitian extension; DC and Nyquist taken as real).
-// Entries with index above kmax are known to be zero and are not read.
-template <int N, typename T>
-__device__ __forceinline__ cplx<T> pack_pair(const cplx<T>* __restrict__ ra, const cplx<T>* __restrict__ rb, int k,
-                                             int kmax) {
-  cplx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-  const int idx = k <= N / 2 ? k : N - k;
-  if (idx <= kmax) {
-    A = ra[idx];
-    B = rb[idx];
-    if (k == 0 || k == N / 2) {
-      A.y = T(0);
-      B.y = T(0);
-    } else if (k > N / 2) {
-      A = cconj(A);
-      B = cconj(B);
-    }
-  }
-  return {A.x - B.y, A.y + B.x};
 }
 
 // ---------------------------------------------------------------------------
@@ -131,35 +123,75 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Inverse rows: half spectra [rows][N/2+1] -> real [rows][N] * scale, stored as S
+// Inverse rows: half spectra [rows][N/2+1] -> real [rows][N] * scale, stored as S,
+// for a batch of smoothing radii.  Items g = radius * groups + group of WB row
+// pairs form a grid-stride loop; the loads of a block's next item are issued
+// into registers before the FFT and stores of the current one.  Radius r reads
+// in + r istride, writes out + r ostride and only reads entries kx <= kmax(r)
+// (the rest are zero after its sharp-k cut).
 // ---------------------------------------------------------------------------
 template <typename T, typename ST, int N>
 __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __restrict__ in, ST* __restrict__ out,
-                                                              long npairs, T scale, int kmax,
-                                                              const cplx<T>* __restrict__ tw, int tstride) {
+                                                              long npairs, long nitems, T scale,
+                                                              const long* __restrict__ cut, long istride,
+                                                              long ostride, const cplx<T>* __restrict__ tw,
+                                                              int tstride) {
   using S = RowShape<N>;
   __shared__ cplx<T> lds[S::WB * N];
   __shared__ cplx<T> twl[N];
   const int t = threadIdx.x;
+  const long groups = (npairs + S::WB - 1) / S::WB;
   load_twiddles<N>(twl, tw, tstride);
-  for (long g = blockIdx.x; g * S::WB < npairs; g += gridDim.x) {
-    const long p0 = g * S::WB;
+  // this thread builds entry k = t of every packed row: it reads index
+  // idx = min(k, N - k) of the two half spectra
+  const int idx = t <= N / 2 ? t : N - t;
+  cplx<T> pa[S::WB], pb[S::WB];
+  const auto load = [&](long g) {
+    const long r = g / groups, p0 = (g % groups) * S::WB;
+    const bool live = idx <= cut[2 * r + 1];
+    const cplx<T>* src = in + r * istride;
 #pragma unroll
     for (int q = 0; q < S::WB; ++q) {
-      const long p = p0 + q;
-      cplx<T> v = {T(0), T(0)};
-      if (p < npairs) v = pack_pair<N>(in + (2 * p) * S::HP, in + (2 * p + 1) * S::HP, t, kmax);
-      lds[q * N + t] = v;
+      pa[q] = {T(0), T(0)};
+      pb[q] = {T(0), T(0)};
+    }
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < S::WB; ++q) {
+        const long p = min(p0 + q, npairs - 1);  // a valid row; rows past the end are not stored
+        pa[q] = src[(2 * p) * S::HP + idx];
+        pb[q] = src[(2 * p + 1) * S::HP + idx];
+      }
+    }
+  };
+  long g = blockIdx.x;
+  if (g < nitems) load(g);
+  for (; g < nitems; g += gridDim.x) {
+    // Z[k] = A[k] + i B[k] (Hermitian extension; DC and Nyquist taken as real)
+#pragma unroll
+    for (int q = 0; q < S::WB; ++q) {
+      cplx<T> A = pa[q], B = pb[q];
+      if (t == 0 || t == N / 2) {
+        A.y = T(0);
+        B.y = T(0);
+      } else if (t > N / 2) {
+        A = cconj(A);
+        B = cconj(B);
+      }
+      lds[q * N + t] = {A.x - B.y, A.y + B.x};
     }
     __syncthreads();
+    const long r = g / groups, p0 = (g % groups) * S::WB;
+    if (g + gridDim.x < nitems) load(g + gridDim.x);
     fft_team<N, +1, T>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    ST* dst = out + r * ostride;
 #pragma unroll
     for (int q = 0; q < S::WB; ++q) {
       const long p = p0 + q;
       if (p < npairs) {
         const cplx<T> v = lds[q * N + t];
-        store_as(out, (2 * p) * N + t, v.x * scale);
-        store_as(out, (2 * p + 1) * N + t, v.y * scale);
+        store_as(dst, (2 * p) * N + t, v.x * scale);
+        store_as(dst, (2 * p + 1) * N + t, v.y * scale);
       }
     }
     __syncthreads();
@@ -176,25 +208,59 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
 //   it are stored (every other column is zero after this pass).
 // MODE 2: y pass of a smoothing (inner index = kx): an entry is read only if
 //   ny^2 + kx^2 <= n2max, the rest is known to be zero.
+// MODE 3: one column (inner index ilim - 1) of each of TI consecutive outer
+//   slices per block (blockIdx.x picks the slices): the Nyquist column of a
+//   forward y pass, so that the main launch only covers full aligned tiles.
 // ---------------------------------------------------------------------------
 // |n|^2 without the z part of flat column i = y * HP + kx of a padded half
 // spectrum; padding columns (kx > N/2) get a value above every cutoff.
+// (32-bit arithmetic: i < N * HP and |n|^2 <= N^2 / 2 fit easily.)
 template <int N>
-__device__ __forceinline__ long column_n2(long i) {
-  const long ky = i / Half<N>::HP, kx = i % Half<N>::HP;
-  const long ny = ky < N / 2 ? ky : ky - N;
-  return kx < Half<N>::H ? ny * ny + kx * kx : 0x7fffffffffffL;
+__device__ __forceinline__ int column_n2(long i) {
+  const int ii = static_cast<int>(i);
+  const int ky = ii / Half<N>::HP, kx = ii % Half<N>::HP;
+  const int ny = ky < N / 2 ? ky : ky - N;
+  return kx < Half<N>::H ? ny * ny + kx * kx : 0x3fffffff;
 }
 
 template <typename T, int N, int DIR, int MODE>
 __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, cplx<T>* dst, long inner, long ilim,
-                                                           long n2max, const cplx<T>* __restrict__ tw, int tstride) {
+                                                           const long* __restrict__ cut, long sstride, long dstride,
+                                                           long nslices, const cplx<T>* __restrict__ tw, int tstride) {
   using A = AxisShape<N>;
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
   const int t = threadIdx.x;
+  // blockIdx.z selects one smoothing radius of a batch: its own cutoff
+  // (n2max, kmax) and its own slice of src / dst
+  long n2max = 0;
+  if constexpr (MODE == 1 || MODE == 2) {
+    n2max = cut[2 * blockIdx.z];
+    if constexpr (MODE == 2) ilim = min(ilim, cut[2 * blockIdx.z + 1] + 1);
+  }
+  src += blockIdx.z * sstride;
+  dst += blockIdx.z * dstride;
+  if constexpr (MODE == 3) {
+    // gathered single columns: column c of the tile is slice blockIdx.x * TI + c
+    const long outer = nslices;
+    for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
+    for (int l = t; l < N * A::TI; l += A::NT) {
+      const int n = l / A::TI, c = l % A::TI;
+      const long o = static_cast<long>(blockIdx.x) * A::TI + c;
+      lds[l] = o < outer ? src[(o * N + n) * inner + ilim - 1] : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    fft_team<N, DIR, T, typename A::Plan>(lds + (t % A::TI), A::TI, t / A::TI, twl, 1);
+    for (int l = t; l < N * A::TI; l += A::NT) {
+      const int n = l / A::TI, c = l % A::TI;
+      const long o = static_cast<long>(blockIdx.x) * A::TI + c;
+      if (o < outer) dst[(o * N + n) * inner + ilim - 1] = lds[l];
+    }
+    return;
+  }
   const long base = static_cast<long>(blockIdx.y) * N * inner;
   const long i0 = static_cast<long>(blockIdx.x) * A::TI;
+  if (i0 >= ilim) return;  // block-uniform
   if constexpr (MODE == 1) {
     bool any = false;  // block-uniform
     for (int c = 0; c < A::TI; ++c) any |= (i0 + c < ilim) && column_n2<N>(i0 + c) <= n2max;
@@ -215,7 +281,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     lds[l] = v;
   }
   __syncthreads();
-  fft_team<N, DIR, T>(lds + (t % A::TI), A::TI, t / A::TI, twl, 1);
+  fft_team<N, DIR, T, typename A::Plan>(lds + (t % A::TI), A::TI, t / A::TI, twl, 1);
   for (int l = t; l < N * A::TI; l += A::NT) {
     const int n = l / A::TI, c = l % A::TI;
     const long i = i0 + c;
@@ -225,79 +291,179 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
   }
 }
 
+// Plain strided pass over full tiles only (columns i0 .. i0 + TI - 1 < ilim),
+// as a grid-stride loop over tiles g = slice * tiles_x + column block: each
+// block issues the global loads of its next tile into registers before the
+// FFT of the current one, so that memory latency overlaps the transform.
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* src, cplx<T>* dst, long inner,
+                                                                long tiles_x, long ntiles,
+                                                                const cplx<T>* __restrict__ tw, int tstride) {
+  using A = AxisShape<N>;
+  constexpr int L = N * A::TI / A::NT;  // elements per thread and tile
+  __shared__ cplx<T> lds[N * A::TI];
+  __shared__ cplx<T> twl[N];
+  const int t = threadIdx.x;
+  const int c = t % A::TI, n0 = t / A::TI;  // element l = t + k NT sits at row n0 + k NT / TI, column c
+  constexpr int NSTEP = A::NT / A::TI;
+  for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
+  cplx<T> pre[L];
+  const auto offset = [&](long g) {
+    const long o = g / tiles_x, i0 = (g % tiles_x) * A::TI;
+    return (o * N + n0) * inner + i0 + c;
+  };
+  long g = blockIdx.x;
+  if (g < ntiles) {
+    const long off = offset(g);
+#pragma unroll
+    for (int k = 0; k < L; ++k) pre[k] = src[off + static_cast<long>(k) * NSTEP * inner];
+  }
+  for (; g < ntiles; g += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
+    __syncthreads();
+    const long off = offset(g);
+    const long gn = g + gridDim.x;
+    if (gn < ntiles) {
+      const long offn = offset(gn);
+#pragma unroll
+      for (int k = 0; k < L; ++k) pre[k] = src[offn + static_cast<long>(k) * NSTEP * inner];
+    }
+    fft_team<N, DIR, T, typename A::Plan>(lds + c, A::TI, n0, twl, 1);
+#pragma unroll
+    for (int k = 0; k < L; ++k) dst[off + static_cast<long>(k) * NSTEP * inner] = lds[t + k * A::NT];
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Forward z pass fused with |X|^2 binning.  src [outer][N][inner] holds the
-// x- and y-transformed spectra (inner = y * (N/2+1) + kx); each block writes
-// FP64 bin sums of w |X|^2 for its tile to part[outer][tile][nbins].
-// Weights w: 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere (half spectrum).
+// Forward z pass fused with |X|^2 binning.  src [outer][N][N * HP] holds the
+// x- and y-transformed spectra (padded rows).  Tiles cover live columns only
+// and keep 128-byte aligned loads: "main" tiles are 16 consecutive kx < KM of
+// one y (KM = the largest multiple of 16 <= N/2), "rest" tiles gather the
+// remaining columns (kx in [KM, N/2], the Nyquist plane for N >= 32) of 16
+// consecutive (y, kx) pairs.  Each block writes FP64 bin sums of w |X|^2 for
+// its tile to part[outer][tile][nbins].  Weights w: 1 on the kx = 0 and
+// kx = N/2 planes, 2 elsewhere (half spectrum).
 // ---------------------------------------------------------------------------
+template <int N, int TI>
+struct BinTiles {
+  static constexpr int H = Half<N>::H;
+  static constexpr int KM = (N / 2) / TI * TI;      // kx covered by main tiles
+  static constexpr int RW = H - KM;                 // rest columns per y
+  static constexpr long MAIN = static_cast<long>(N) * (KM / TI);
+  static constexpr long REST = (static_cast<long>(N) * RW + TI - 1) / TI;
+  static constexpr long COUNT = MAIN + REST;
+  // (ky, kx) of column cc of a tile, or ky = -1 past the end
+  __device__ static void column(long tile, int cc, int& ky, int& kx) {
+    if constexpr (KM > 0) {
+      if (tile < MAIN) {
+        ky = static_cast<int>(tile / (KM / TI));
+        kx = static_cast<int>(tile % (KM / TI)) * TI + cc;
+        return;
+      }
+    }
+    {
+      const long r = (tile - MAIN) * TI + cc;
+      ky = r < static_cast<long>(N) * RW ? static_cast<int>(r / RW) : -1;
+      kx = KM + static_cast<int>(r % RW);
+    }
+  }
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src, long inner,
+__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src, long nitems,
                                                                 const int8_t* __restrict__ bintab, int nbins,
                                                                 double* __restrict__ part,
                                                                 const cplx<T>* __restrict__ tw, int tstride) {
   using A = AxisShape<N>;
-  constexpr int H = Half<N>::H, HP = Half<N>::HP;
-  constexpr int M = N / A::TS;           // contiguous outputs per thread
-  constexpr int NW = A::NT / 64;         // waves per block
+  using BT = BinTiles<N, A::TI>;
+  constexpr int HP = Half<N>::HP;
+  constexpr long PLANE = static_cast<long>(N) * HP;  // stride between z planes
+  constexpr int M = N / A::TS;                       // contiguous outputs per thread
+  constexpr int NW = A::NT / 64;                     // waves per block
+  constexpr int L = N * A::TI / A::NT;               // loaded elements per thread and tile
+  constexpr int NSTEP = A::NT / A::TI;
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
-  __shared__ double wacc[NW][kMaxBins];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const long base = static_cast<long>(blockIdx.y) * N * inner;
-  const long i0 = static_cast<long>(blockIdx.x) * A::TI;
+  const int cc = t % A::TI, j = t / A::TI;  // loads: rows j + k NSTEP; FFT: team member j of column cc
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
-  for (int b = lane; b < nbins; b += 64) wacc[wave][b] = 0.0;
-  for (int l = t; l < N * A::TI; l += A::NT) {
-    const int n = l / A::TI, c = l % A::TI;
-    const long i = i0 + c;
-    lds[l] = (i < inner && i % HP < H) ? src[base + n * inner + i] : cplx<T>{T(0), T(0)};
-  }
-  __syncthreads();
-  const int c = t % A::TI, j = t / A::TI;
-  fft_team<N, -1, T>(lds + c, A::TI, j, twl, 1);
-
-  const long i = i0 + c;
-  int bin[M];
-  T val[M];
-  int bmin = kMaxBins, bmax = -1;
-  {
-    const int ky = static_cast<int>(i / HP), kx = static_cast<int>(i % HP);
-    const long ny = ky < N / 2 ? ky : ky - N;
-    const long cyx = ny * ny + static_cast<long>(kx) * kx;
-    const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
-    const bool col = i < inner && kx < H;
+  // item g = spectrum * COUNT + tile; its column for this thread (ky < 0: none)
+  cplx<T> pre[L];
+  const auto load = [&](long g) {
+    int ky, kx;
+    BT::column(g % BT::COUNT, cc, ky, kx);
+    const bool live = ky >= 0;
+    const long off = (g / BT::COUNT) * N * PLANE + static_cast<long>(j) * PLANE +
+                     static_cast<long>(live ? ky : 0) * HP + kx;  // a valid address either way
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int kz = j * M + m;
-      const long nz = kz < N / 2 ? kz : kz - N;
-      const cplx<T> x = lds[kz * A::TI + c];
-      int b = -1;
-      if (col) b = bintab[nz * nz + cyx];
-      bin[m] = b;
-      val[m] = w * (x.x * x.x + x.y * x.y);
-      if (b >= 0) {
-        bmin = min(bmin, b);
-        bmax = max(bmax, b);
+    for (int k = 0; k < L; ++k) {
+      const cplx<T> v = src[off + static_cast<long>(k) * NSTEP * PLANE];
+      pre[k] = live ? v : cplx<T>{T(0), T(0)};
+    }
+  };
+  long g = blockIdx.x;
+  if (g < nitems) load(g);
+  for (; g < nitems; g += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
+    __syncthreads();
+    if (g + gridDim.x < nitems) load(g + gridDim.x);
+    fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
+
+    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1
+    int bin[M];
+    T val[M];
+    {
+      int ky, kx;
+      BT::column(g % BT::COUNT, cc, ky, kx);
+      const int ny = ky < N / 2 ? ky : ky - N;
+      const int cyx = ny * ny + kx * kx;
+      const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
+      const bool col = ky >= 0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int kz = j * M + m;
+        const int nz = kz < N / 2 ? kz : kz - N;
+        const cplx<T> x = lds[kz * A::TI + cc];
+        bin[m] = col ? bintab[nz * nz + cyx] : -1;
+        val[m] = w * (x.x * x.x + x.y * x.y);
       }
     }
-  }
-  bmin = wave_min(bmin);
-  bmax = wave_max(bmax);
-  for (int b = bmin; b <= bmax; ++b) {
-    T s = T(0);
+    // Bin sums through LDS (the FFT buffer, reused): each thread adds the runs
+    // of equal bins along its kz range (|nz| is monotone there, so a run is
+    // rarely broken) into its own column of slot[bin][thread], then one wave
+    // per bin sums the NT columns in a fixed order (deterministic).
+    constexpr int CAP = 2 * N * A::TI / A::NT;  // bins per chunk: T values in the FFT buffer per thread
+    T* slot = reinterpret_cast<T*>(lds);
+    for (int b0 = 0; b0 < nbins; b0 += CAP) {
+      const int nb = min(CAP, nbins - b0);
+      __syncthreads();  // the FFT buffer (or the previous chunk) is no longer read
+      for (int b = 0; b < nb; ++b) slot[b * A::NT + t] = T(0);
+      int cur = -1;
+      T run = T(0);
 #pragma unroll
-    for (int m = 0; m < M; ++m) s += bin[m] == b ? val[m] : T(0);
-    const T d = wave_sum(s);
-    if (lane == 0) wacc[wave][b] += static_cast<double>(d);
-  }
-  __syncthreads();
-  const long tile = static_cast<long>(blockIdx.y) * gridDim.x + blockIdx.x;
-  for (int b = t; b < nbins; b += A::NT) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += wacc[w][b];
-    part[tile * nbins + b] = s;
+      for (int m = 0; m < M; ++m) {
+        if (bin[m] != cur) {
+          if (cur >= b0 && cur < b0 + nb) slot[(cur - b0) * A::NT + t] += run;
+          run = T(0);
+          cur = bin[m];
+        }
+        run += val[m];
+      }
+      if (cur >= b0 && cur < b0 + nb) slot[(cur - b0) * A::NT + t] += run;
+      __syncthreads();
+      for (int b = wave; b < nb; b += NW) {
+        T sum = T(0);
+#pragma unroll
+        for (int i = 0; i < A::NT / 64; ++i) sum += slot[b * A::NT + i * 64 + lane];
+        const double d = wave_sum(static_cast<double>(sum));
+        if (lane == 0) part[g * nbins + b0 + b] = d;
+      }
+    }
+    __syncthreads();  // slots are read before the next tile is stored
   }
 }
 
@@ -311,28 +477,12 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
 // loads.  Unflagged cells keep x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)).
 // ---------------------------------------------------------------------------
 template <typename T, int NR>
-__device__ __forceinline__ T cell_xhi(const T (&d)[NR], T cell, int nr, const WalkerConst<T>& c,
-                                      const T* __restrict__ thr_w, T dc) {
+__device__ __forceinline__ T cell_xhi(const T (&d)[NR], T cell, const WalkerConst<T>& c, const T* thr_w, T dc) {
   // OR over radii as wave-wide lane masks: one compare into a scalar mask per
-  // radius.  Radii before the walker's first are skipped by uniform branches;
-  // their thresholds, like those past the ladder end, are +inf, so the result
-  // does not depend on the skipping.
-  T th[NR];
-#pragma unroll
-  for (int j = 0; j < NR; ++j) th[j] = thr_w[j];
-  // blocks of 8 radii that lie wholly before the walker's first radius or
-  // past the ladder end are skipped (one uniform branch per block); inside a
-  // block every radius is tested, the +inf thresholds making the extra ones
-  // irrelevant
+  // radius; thresholds of radii the walker does not use are +inf
   unsigned long long m = 0;
-  const int first = c.first;
 #pragma unroll
-  for (int g = 0; g < NR; g += 8) {
-    if (first < g + 8 && g < nr) {
-#pragma unroll
-      for (int j = g; j < g + 8 && j < NR; ++j) m |= __ballot(d[j] >= th[j]);
-    }
-  }
+  for (int j = 0; j < NR; ++j) m |= __ballot(d[j] >= thr_w[j]);
   const bool flag = (m >> __lane_id()) & 1ull;
   T x = T(1);
   if (flag) {
@@ -343,18 +493,15 @@ __device__ __forceinline__ T cell_xhi(const T (&d)[NR], T cell, int nr, const Wa
   return x;
 }
 
+// Loads delta_R of one cell for every radius slot.  Slots past the ladder end
+// repeat the last radius (their thresholds are +inf, so they never flag), so
+// that all loads are unconditional and issue back to back.
 template <typename T, typename S, int NR>
 __device__ __forceinline__ void load_radii(const S* __restrict__ dR, size_t n3, size_t cell, int nr, T (&d)[NR],
                                            T& dcell) {
-  dcell = T(0);
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    d[j] = T(0);
-    if (j < nr) {
-      d[j] = load_as<T>(dR, j * n3 + cell);
-      if (j == nr - 1) dcell = d[j];
-    }
-  }
+  for (int j = 0; j < NR; ++j) d[j] = load_as<T>(dR, static_cast<size_t>(j < nr ? j : nr - 1) * n3 + cell);
+  dcell = load_as<T>(dR, static_cast<size_t>(nr - 1) * n3 + cell);
 }
 
 // Threads and LDS batches of the ionisation pass: one cell per thread over a
@@ -371,6 +518,16 @@ template <>
 struct IonPlan<256> {
   using type = Radices<8, 8, 4>;
 };
+
+// Waves per SIMD the compiler must leave room for in the FP32 ionisation pass
+// at N = 128 and 256 (it then keeps the kernel within 512 / 6 = 85 VGPRs):
+// measured on the 256^3, 64-walker workload, occupancy matters more there than
+// the few spills it costs.  Other shapes are limited by LDS or block size
+// before registers, and FP64 needs the registers.
+template <typename T, int N>
+constexpr int ion_waves_per_simd() {
+  return (sizeof(T) == 4 && (N == 128 || N == 256)) ? 6 : 1;
+}
 
 template <int N>
 struct IonShape {
@@ -391,7 +548,7 @@ struct IonShape {
 // one complex row.  Output: spec[w][row][kx] for w < nw, and per-block x_HI
 // sums xpart[w][block].
 template <typename T, typename S, int N>
-__global__ __launch_bounds__(IonShape<N>::NT) void k_ion_rows(
+__global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ delta, int nr, const WalkerConst<T>* __restrict__ wc,
     const T* __restrict__ thr, int nw, T tb, T dc, cplx<T>* __restrict__ spec, double* __restrict__ xpart,
     const cplx<T>* __restrict__ tw, int tstride) {
@@ -400,10 +557,12 @@ __global__ __launch_bounds__(IonShape<N>::NT) void k_ion_rows(
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
   __shared__ cplx<T> lds[IS::WB * N];
   __shared__ cplx<T> twl[N];
-  __shared__ T wsum[IS::WB][IS::NT >= 64 ? IS::NW : IS::NT];
+  // x_HI partial sums of a batch: one per 16-lane row (NT >= 64) or per thread
+  constexpr int NPS = IS::NT >= 64 ? IS::NT / 16 : IS::NT;
+  __shared__ T wsum[IS::WB][NPS];
   __shared__ double acc[kMaxGroup];
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
+  const int lane = t & 63;
   const int row = t / N, x = t % N;
   T* ldsr = reinterpret_cast<T*>(lds);
   for (int w = t; w < kMaxGroup; w += IS::NT) acc[w] = 0.0;
@@ -419,11 +578,11 @@ __global__ __launch_bounds__(IonShape<N>::NT) void k_ion_rows(
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        const T xh = cell_xhi<T, kNrMax>(d, dcell, nr, wc[w], thr + static_cast<size_t>(w) * kNrMax, dc);
+        const T xh = cell_xhi<T, kNrMax>(d, dcell, wc[w], thr + static_cast<size_t>(w) * kNrMax, dc);
         ldsr[2 * (q * N + x) + row] = tb * xh * od;
         if constexpr (IS::NT >= 64) {
-          const T s = wave_sum(xh);
-          if (lane == 0) wsum[q][wave] = s;
+          const T s = row_sum(xh);
+          if ((lane & 15) == 0) wsum[q][t >> 4] = s;
         } else {
           wsum[q][t] = xh;
         }
@@ -431,7 +590,7 @@ __global__ __launch_bounds__(IonShape<N>::NT) void k_ion_rows(
       __syncthreads();
       if (t < IS::WB && w0 + t < nw) {
         double s = 0.0;
-        for (int k = 0; k < (IS::NT >= 64 ? IS::NW : IS::NT); ++k) s += static_cast<double>(wsum[t][k]);
+        for (int k = 0; k < NPS; ++k) s += static_cast<double>(wsum[t][k]);
         acc[w0 + t] += s;
       }
       fft_team<N, -1, T, typename IS::Plan>(lds + (t / IS::TS) * N, 1, t % IS::TS, twl, 1);
@@ -465,7 +624,7 @@ __global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, c
     T d[kNrMax];
     T dcell;
     load_radii<T, S>(dR, N3, cell, nr, d, dcell);
-    const T x = cell_xhi<T, kNrMax>(d, dcell, nr, c, thr, dc);
+    const T x = cell_xhi<T, kNrMax>(d, dcell, c, thr, dc);
     if (xhi) xhi[cell] = x;
     if (dtb) dtb[cell] = tb * x * (T(1) + delta[cell]);
   }
@@ -550,6 +709,14 @@ hipError_t with_storage(int storage, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// Blocks of the grid-stride pipelined passes: several resident blocks per CU,
+// each working through many tiles.  (The CPU emulation used by the tests
+// builds with a tiny value so that every block walks through several items.)
+#ifndef XS21_PIPE_BLOCKS
+#define XS21_PIPE_BLOCKS 2048
+#endif
+constexpr long kPipeBlocks = XS21_PIPE_BLOCKS;
+
 unsigned grid_for(long work, long cap) { return static_cast<unsigned>(work < cap ? (work > 0 ? work : 1) : cap); }
 
 }  // namespace
@@ -566,6 +733,16 @@ int axis_tile(int n) {
 long axis_tiles(int n, long inner) {
   const int ti = axis_tile(n);
   return ti > 0 ? (inner + ti - 1) / ti : 0;
+}
+
+long bins_tiles(int n) {
+  long count = 0;
+  (void)with_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    count = BinTiles<N, AxisShape<N>::TI>::COUNT;
+    return hipSuccess;
+  });
+  return count;
 }
 
 int ion_grid(int n) { return static_cast<int>(grid_for(static_cast<long>(n) * n / 2, 4096)); }
@@ -601,7 +778,9 @@ hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nro
 }
 
 hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* out, long nrows, double scale,
-                           int kmax, const void* tw, int ntab, hipStream_t s) {
+                           const long* cut, int batch, long istride, long ostride, const void* tw, int ntab,
+                           hipStream_t s) {
+  if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_storage<T>(storage, [&](auto sv) {
@@ -609,10 +788,10 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
       return with_n(n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
         const long npairs = nrows / 2;
-        const long groups = (npairs + RowShape<N>::WB - 1) / RowShape<N>::WB;
-        hipLaunchKernelGGL((k_rows_c2r<T, ST, N>), dim3(grid_for(groups, 8192)), dim3(RowShape<N>::NT), 0, s,
-                           static_cast<const cplx<T>*>(in), static_cast<ST*>(out), npairs, static_cast<T>(scale),
-                           kmax, static_cast<const cplx<T>*>(tw), ntab / N);
+        const long items = (npairs + RowShape<N>::WB - 1) / RowShape<N>::WB * batch;
+        hipLaunchKernelGGL((k_rows_c2r<T, ST, N>), dim3(grid_for(items, kPipeBlocks)), dim3(RowShape<N>::NT), 0, s,
+                           static_cast<const cplx<T>*>(in), static_cast<ST*>(out), npairs, items,
+                           static_cast<T>(scale), cut, istride, ostride, static_cast<const cplx<T>*>(tw), ntab / N);
         return hipGetLastError();
       });
     });
@@ -620,43 +799,67 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
 }
 
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
-                       long ilim, long n2max, const void* tw, int ntab, hipStream_t s) {
-  if (ilim < 1 || ilim > inner || mode < 0 || mode > 2) return hipErrorInvalidValue;
+                       long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
+                       hipStream_t s) {
+  if (ilim < 1 || ilim > inner || mode < 0 || mode > 2 || (mode != 0 && !cut) || batch < 1 || batch > 65535 ||
+      outer > 65535)
+    return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
       constexpr int N = decltype(nc)::value;
       using A = AxisShape<N>;
-      const dim3 grid(static_cast<unsigned>((ilim + A::TI - 1) / A::TI), static_cast<unsigned>(outer));
+      const dim3 grid(static_cast<unsigned>((ilim + A::TI - 1) / A::TI), static_cast<unsigned>(outer),
+                      static_cast<unsigned>(batch));
       const auto* sp = static_cast<const cplx<T>*>(src);
       auto* dp = static_cast<cplx<T>*>(dst);
       const auto* tp = static_cast<const cplx<T>*>(tw);
       const int ts = ntab / N;
       if (dir < 0) {
-        hipLaunchKernelGGL((k_axis<T, N, -1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, n2max, tp, ts);
+        // forward: when the last column sits alone in its tile (the Nyquist
+        // column of a half spectrum), full tiles go first and that column of
+        // every slice is gathered TI slices per block
+        const long full = ilim / A::TI * A::TI;
+        if (mode == 0 && batch == 1 && ilim - full <= 1 && full > 0) {
+          const long ntiles = full / A::TI * outer;
+          hipLaunchKernelGGL((k_axis_pipe<T, N, -1>), dim3(grid_for(ntiles, kPipeBlocks)), dim3(A::NT), 0, s, sp, dp,
+                             inner, full / A::TI, ntiles, tp, ts);
+          if (ilim > full) {
+            const dim3 g2(static_cast<unsigned>((outer + A::TI - 1) / A::TI), 1, 1);
+            hipLaunchKernelGGL((k_axis<T, N, -1, 3>), g2, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride,
+                               dstride, outer, tp, ts);
+          }
+        } else {
+          hipLaunchKernelGGL((k_axis<T, N, -1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride,
+                             dstride, outer, tp, ts);
+        }
       } else if (mode == 1) {
-        hipLaunchKernelGGL((k_axis<T, N, +1, 1>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, n2max, tp, ts);
+        hipLaunchKernelGGL((k_axis<T, N, +1, 1>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
+                           outer, tp, ts);
       } else if (mode == 2) {
-        hipLaunchKernelGGL((k_axis<T, N, +1, 2>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, n2max, tp, ts);
+        hipLaunchKernelGGL((k_axis<T, N, +1, 2>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
+                           outer, tp, ts);
       } else {
-        hipLaunchKernelGGL((k_axis<T, N, +1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, n2max, tp, ts);
+        hipLaunchKernelGGL((k_axis<T, N, +1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
+                           outer, tp, ts);
       }
       return hipGetLastError();
     });
   });
 }
 
-hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, long inner, const int8_t* bintab,
-                            int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
-  if (nbins < 1 || nbins > kMaxBins) return hipErrorInvalidValue;
+hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const int8_t* bintab, int nbins,
+                            double* part, const void* tw, int ntab, hipStream_t s) {
+  if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
       constexpr int N = decltype(nc)::value;
       using A = AxisShape<N>;
-      const dim3 grid(static_cast<unsigned>((inner + A::TI - 1) / A::TI), static_cast<unsigned>(outer));
-      hipLaunchKernelGGL((k_axis_bins<T, N>), grid, dim3(A::NT), 0, s, static_cast<const cplx<T>*>(src), inner,
-                         bintab, nbins, part, static_cast<const cplx<T>*>(tw), ntab / N);
+      const long items = BinTiles<N, A::TI>::COUNT * outer;
+      hipLaunchKernelGGL((k_axis_bins<T, N>), dim3(grid_for(items, kPipeBlocks)), dim3(A::NT), 0, s,
+                         static_cast<const cplx<T>*>(src), items, bintab, nbins, part,
+                         static_cast<const cplx<T>*>(tw), ntab / N);
       return hipGetLastError();
     });
   });

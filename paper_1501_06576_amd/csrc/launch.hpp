@@ -14,6 +14,7 @@ constexpr int kBF16 = 2;
 
 int axis_tile(int n);                   // inner columns per block of the strided passes
 long axis_tiles(int n, long inner);     // blocks along the inner dimension
+long bins_tiles(int n);                 // blocks per spectrum of the binning z pass
 int ion_grid(int n);                    // blocks of the ionisation pass
 int max_group();                        // walkers per ionisation launch
 int max_radii();                        // radii per ladder
@@ -24,20 +25,27 @@ int half_pitch(int n);                  // row pitch (complex values) of a half 
 // Real rows [nrows][n] of `dtype` -> half-spectrum rows [nrows][half_pitch(n)].
 hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nrows, const void* tw, int ntab,
                            hipStream_t s);
-// Half-spectrum rows -> real rows * scale, stored as `storage`; entries with
-// kx > kmax are taken as zero without being read.
+// Half-spectrum rows -> real rows * scale, stored as `storage`, for `batch`
+// radii: radius b reads in + b * istride and writes out + b * ostride
+// (elements); entries with kx > cut[2 b + 1] (its kmax) are taken as zero
+// without being read.
 hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* out, long nrows, double scale,
-                           int kmax, const void* tw, int ntab, hipStream_t s);
+                           const long* cut, int batch, long istride, long ostride, const void* tw, int ntab,
+                           hipStream_t s);
 // Transform along the middle axis of [outer][n][inner] for columns < ilim
-// (dir -1 forward, +1 inverse).  mode 0 plain; mode 1 the z pass of a sharp-k
-// smoothing (|n|^2 <= n2max kept, columns outside the disk skipped); mode 2
-// the y pass of a smoothing (only entries with ny^2 + kx^2 <= n2max read).
+// (dir -1 forward, +1 inverse), for `batch` slices: slice b reads src + b *
+// sstride and writes dst + b * dstride (elements).  mode 0 plain; mode 1 the
+// z pass of a sharp-k smoothing with cutoff |n|^2 <= cut[2 b] (columns
+// outside the disk skipped); mode 2 the y pass of a smoothing (only entries
+// with ny^2 + kx^2 <= cut[2 b] read, columns kx <= cut[2 b + 1]).  cut is a
+// device array of (n2max, kmax) pairs, unused by mode 0.
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
-                       long ilim, long n2max, const void* tw, int ntab, hipStream_t s);
-// Forward z pass of [outer][n][n*(n/2+1)] fused with |X|^2 binning into
-// part[outer][axis_tiles][nbins] (FP64).
-hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, long inner, const int8_t* bintab,
-                            int nbins, double* part, const void* tw, int ntab, hipStream_t s);
+                       long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
+                       hipStream_t s);
+// Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] fused with
+// |X|^2 binning into part[outer][bins_tiles(n)][nbins] (FP64).
+hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const int8_t* bintab, int nbins,
+                            double* part, const void* tw, int ntab, hipStream_t s);
 // Ionisation + dT_b + forward x pass for nw walkers on one box.
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,
                       const void* thr, int nw, double tb, double dc, void* spec, double* xpart, const void* tw,

@@ -75,6 +75,17 @@ template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   return wave_reduce(v, T(0), [](T a, T b) { return a + b; });
 }
+
+// Sum of v over the 16 lanes of each row of the wave, returned in every lane
+// of that row (four DPP steps, fixed order).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  const auto add = [](T a, T b) { return a + b; };
+  v = dpp_step<kDppQuadSwap1, 0xf>(v, T(0), add);
+  v = dpp_step<kDppQuadSwap2, 0xf>(v, T(0), add);
+  v = dpp_step<kDppHalfMirror, 0xf>(v, T(0), add);
+  return dpp_step<kDppRowMirror, 0xf>(v, T(0), add);
+}
 __device__ __forceinline__ int wave_min(int v) {
   return wave_reduce(v, 0x7fffffff, [](int a, int b) { return a < b ? a : b; });
 }
@@ -85,10 +96,11 @@ __device__ __forceinline__ int wave_max(int v) {
 // erfc(x) = t exp(-z^2 + P(t)), t = 1 / (1 + z/2), z = |x|, P a degree-9
 // Chebyshev fit (Press, Teukolsky, Vetterling & Flannery, Numerical Recipes,
 // 2nd ed., section 6.2, "erfcc"): fractional error below 1.2e-7 for all x;
-// erfc(-z) = 2 - erfc(z).
+// erfc(-z) = 2 - erfc(z).  The reciprocal and exponential are the hardware's
+// approximate ones (about 1 ulp each).
 __device__ __forceinline__ float erfc_fast(float x) {
   const float z = fabsf(x);
-  const float t = __fdividef(1.0f, 1.0f + 0.5f * z);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);  // v_rcp_f32, 1 ulp
   float p = 0.17087277f;
   p = fmaf(p, t, -0.82215223f);
   p = fmaf(p, t, 1.48851587f);

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <list>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,7 @@ int main(int argc, char** argv) {
   std::vector<xs21_walker> walkers;
   std::vector<int> box_dtype, box_n;
   std::vector<std::vector<char>> box_data;
+  std::list<std::vector<char>> staged;  // inputs of queued device work, kept to the end
   std::string out = ".";
   xs21_ctx* ctx = nullptr;
   void* ws = nullptr;
@@ -111,23 +113,30 @@ int main(int argc, char** argv) {
       CHECK(xs21_prepare(ctx, ws, bytes, storage, max_walkers, max_plain));
       std::printf("workspace %zu\n", bytes);
     } else if (cmd == "batch") {
+      // batch <nbmax> [tag]: every walker on every box, outputs batch<tag>_*.bin
       const int nb = static_cast<int>(box_n.size());
       std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
       int nbmax = 0;
-      for (int i = 0; i < nb; ++i) {
-        bx[i] = i;
-        double km[64];
-        (void)km;
-        nbmax = std::max(nbmax, 0);
-      }
-      // nbmax from the spec's boxes: ask the library via k_mean lengths is not possible; read from args
-      is >> nbmax;
+      std::string tag;
+      is >> nbmax >> tag;
       const int nw = static_cast<int>(walkers.size());
       std::vector<double> pk(static_cast<size_t>(nw) * nb * nbmax, -1.0), xm(static_cast<size_t>(nw) * nb, -1.0);
       CHECK(xs21_eval_batch(ctx, bx.data(), nb, walkers.data(), nw, pk.data(), xm.data()));
       CHECK(xs21_sync(ctx));
-      write_file(out + "/batch_pk.bin", pk.data(), pk.size() * 8);
-      write_file(out + "/batch_xhi.bin", xm.data(), xm.size() * 8);
+      write_file(out + "/batch" + tag + "_pk.bin", pk.data(), pk.size() * 8);
+      write_file(out + "/batch" + tag + "_xhi.bin", xm.data(), xm.size() * 8);
+    } else if (cmd == "resmooth") {
+      // resmooth <box> <file|->: new density (same dtype and size) or the current one
+      int b;
+      std::string ff;
+      is >> b >> ff;
+      const void* src = nullptr;
+      if (ff != "-") {
+        staged.push_back(read_file(ff));
+        src = staged.back().data();
+      }
+      CHECK(xs21_resmooth(ctx, b, src));
     } else if (cmd == "plain") {
       int b, w;
       std::string rf;

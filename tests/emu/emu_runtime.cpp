@@ -5,7 +5,11 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <deque>
+#include <map>
 #include <memory>
+#include <random>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -98,19 +102,89 @@ void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg) {
       tl_thread = {static_cast<unsigned>(t), 0, 0};
       tl_lane = t % 64;
       tl_wave = &g_waves[t / 64];
-      for (unsigned by = 0; by < grid.y; ++by)
-        for (unsigned bx = 0; bx < grid.x; ++bx) {
-          tl_block = {bx, by, 0};
-          body(arg);
-          g_block_bar->arrive_and_wait();
-        }
+      for (unsigned bz = 0; bz < grid.z; ++bz)
+        for (unsigned by = 0; by < grid.y; ++by)
+          for (unsigned bx = 0; bx < grid.x; ++bx) {
+            tl_block = {bx, by, bz};
+            body(arg);
+            g_block_bar->arrive_and_wait();
+          }
     });
   }
   for (auto& x : th) x.join();
 }
 }  // namespace hipemu
 
-struct hipemu_event { int dummy; };
+struct hipemu_event {
+  long last = -1;  // id of the latest record operation issued for this event
+};
+
+namespace hipemu {
+struct Op {
+  enum Kind { kWork, kRecord, kWait } kind;
+  std::function<void()> work;
+  long id;  // record id (kRecord) or awaited record id (kWait)
+};
+std::map<hipStream_t, std::deque<Op>> g_queues;  // nullptr: the default stream
+std::vector<char> g_done;                        // per record id: executed
+std::mt19937_64 g_rng;
+int g_mode = -1;  // 0: eager, 1: deferred with random interleaving
+
+int mode() {
+  if (g_mode < 0) {
+    const char* e = std::getenv("XS21_EMU_STREAMS");
+    std::string v = e ? e : "random:1";
+    if (v == "eager") {
+      g_mode = 0;
+    } else {
+      g_mode = 1;
+      const auto colon = v.find(':');
+      g_rng.seed(colon == std::string::npos ? 1 : std::stoull(v.substr(colon + 1)));
+    }
+  }
+  return g_mode;
+}
+
+bool runnable(const std::deque<Op>& q) {
+  return !q.empty() && (q.front().kind != Op::kWait || g_done[q.front().id]);
+}
+
+// Runs the head operation of one runnable queue (chosen at random); false if none is runnable.
+bool step() {
+  std::vector<std::deque<Op>*> ready;
+  for (auto& kv : g_queues)
+    if (runnable(kv.second)) ready.push_back(&kv.second);
+  if (ready.empty()) return false;
+  auto& q = *ready[ready.size() == 1 ? 0 : g_rng() % ready.size()];
+  Op op = std::move(q.front());
+  q.pop_front();
+  if (op.kind == Op::kWork) op.work();
+  if (op.kind == Op::kRecord) g_done[op.id] = 1;
+  return true;
+}
+
+template <typename P>
+void drain_until(P done) {
+  while (!done())
+    if (!step()) {
+      std::fprintf(stderr, "emulated streams: deadlock (a wait can never be satisfied)\n");
+      std::abort();
+    }
+}
+
+bool all_empty() {
+  for (auto& kv : g_queues)
+    if (!kv.second.empty()) return false;
+  return true;
+}
+
+void push(hipStream_t s, Op op) {
+  g_queues[s].push_back(std::move(op));
+  if (mode() == 0) drain_until(all_empty);
+}
+
+void enqueue(hipStream_t s, std::function<void()> op) { push(s, Op{Op::kWork, std::move(op), -1}); }
+}  // namespace hipemu
 
 hipError_t hipGetLastError() {
   hipError_t e = hipemu::last_error();
@@ -124,17 +198,61 @@ hipError_t hipMalloc(void** p, size_t bytes) { *p = std::malloc(bytes); return *
 hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
 hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) { return hipMalloc(p, bytes); }
 hipError_t hipHostFree(void* p) { return hipFree(p); }
-hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t) {
-  std::memmove(dst, src, bytes);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t s) {
+  hipemu::enqueue(s, [=] { std::memmove(dst, src, bytes); });
   return hipSuccess;
 }
-hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind k) { return hipMemcpyAsync(dst, src, bytes, k, nullptr); }
-hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t) { std::memset(dst, v, bytes); return hipSuccess; }
-hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
-hipError_t hipDeviceSynchronize() { return hipSuccess; }
-hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = new hipemu_event{0}; return hipSuccess; }
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind k) {
+  hipMemcpyAsync(dst, src, bytes, k, nullptr);
+  return hipDeviceSynchronize();
+}
+hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t s) {
+  hipemu::enqueue(s, [=] { std::memset(dst, v, bytes); });
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t s) {
+  hipemu::drain_until([s] { return hipemu::g_queues[s].empty(); });
+  return hipSuccess;
+}
+hipError_t hipDeviceSynchronize() {
+  hipemu::drain_until(hipemu::all_empty);
+  return hipSuccess;
+}
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+  *s = new char;  // a unique handle
+  hipemu::g_queues[*s];
+  return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+  hipStreamSynchronize(s);
+  hipemu::g_queues.erase(s);
+  delete static_cast<char*>(s);
+  return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = new hipemu_event; return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { return hipEventCreateWithFlags(e, 0); }
-hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
-hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
-hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+  e->last = static_cast<long>(hipemu::g_done.size());
+  hipemu::g_done.push_back(0);
+  hipemu::push(s, hipemu::Op{hipemu::Op::kRecord, nullptr, e->last});
+  return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+  // waiting for an event that was never recorded completes at once
+  if (e->last >= 0) hipemu::push(s, hipemu::Op{hipemu::Op::kWait, nullptr, e->last});
+  return hipSuccess;
+}
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  if (e->last >= 0) {
+    const long id = e->last;
+    hipemu::drain_until([id] { return hipemu::g_done[id] != 0; });
+  }
+  return hipSuccess;
+}
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+  hipEventSynchronize(a);
+  hipEventSynchronize(b);
+  *ms = 0.f;
+  return hipSuccess;
+}
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }

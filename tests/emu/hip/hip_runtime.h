@@ -6,6 +6,13 @@
 // block runs as an OS thread; __syncthreads is a barrier over the block and
 // wave intrinsics exchange values through a per-wave slot array.  Blocks run
 // one after another, so __shared__ maps to function-static storage.
+//
+// Streams are queues of deferred operations (launches, copies, event records
+// and waits).  Work runs only when the host synchronises; the scheduler then
+// interleaves the streams' queues in a seeded random order that respects
+// stream order and event waits (XS21_EMU_STREAMS = "random:<seed>", the
+// default "random:1", or "eager" to run every operation at issue), so that a
+// missing dependency between streams shows up as a wrong result.
 #pragma once
 
 #include <stdint.h>
@@ -16,6 +23,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <tuple>
 #include <utility>
 
@@ -39,6 +48,7 @@ typedef struct hipemu_event* hipEvent_t;
 typedef enum { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
 #define hipEventDisableTiming 2u
+#define hipStreamNonBlocking 1u
 #define hipHostMallocDefault 0u
 
 struct dim3 {
@@ -57,6 +67,7 @@ int lane_id();
 unsigned long long wave_ballot(bool pred);
 int wave_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
 void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg);
+void enqueue(hipStream_t s, std::function<void()> op);
 hipError_t last_error(hipError_t set = -1);
 }  // namespace hipemu
 
@@ -91,6 +102,7 @@ inline int __builtin_amdgcn_readlane(int v, int lane) {
 inline int __float_as_int(float f) { return __builtin_bit_cast(int, f); }
 inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
 inline float __fdividef(float a, float b) { return a / b; }
+inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
 inline float __expf(float x) { return expf(x); }
 
 using std::max;
@@ -108,12 +120,13 @@ struct Launch {
 };
 
 template <typename... KArgs, typename... Args>
-inline hipError_t launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t, hipStream_t, Args&&... args) {
-  if (block.x * block.y * block.z > 1024 || block.y != 1 || block.z != 1 || grid.z != 1 || grid.x == 0 || grid.y == 0)
+inline hipError_t launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t, hipStream_t stream, Args&&... args) {
+  if (block.x * block.y * block.z > 1024 || block.y != 1 || block.z != 1 || grid.x == 0 || grid.y == 0 || grid.z == 0)
     return last_error(hipErrorInvalidValue);
   using Tup = std::tuple<KArgs...>;
-  Launch<void (*)(KArgs...), Tup> l{k, Tup(static_cast<KArgs>(args)...)};
-  run_grid(grid, block, &Launch<void (*)(KArgs...), Tup>::body, &l);
+  using L = Launch<void (*)(KArgs...), Tup>;
+  auto l = std::make_shared<L>(L{k, Tup(static_cast<KArgs>(args)...)});
+  enqueue(stream, [l, grid, block] { run_grid(grid, block, &L::body, l.get()); });
   return hipSuccess;
 }
 }  // namespace hipemu
@@ -134,6 +147,9 @@ hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKin
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
 hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t s);
 hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned flags);
+hipError_t hipStreamDestroy(hipStream_t s);
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t hipDeviceSynchronize();
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
 hipError_t hipEventCreate(hipEvent_t* e);

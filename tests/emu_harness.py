@@ -36,7 +36,9 @@ def build() -> str:
     if not _stale():
         return BIN
     os.makedirs(os.path.dirname(BIN), exist_ok=True)
+    # XS21_PIPE_BLOCKS=3: grid-stride kernels run 3 blocks, each over many items
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
+           "-DXS21_PIPE_BLOCKS=3",
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], "-x", "none", *SRC[1:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -18,10 +18,10 @@ EDGE = [(30.0, 15.0, 5e4), (100.0, 20.0, 1e4), (5.0, 5.0, 1e6), (0.4, 12.0, 2e4)
         (0.8, 9.0, 2e4)]
 
 
-def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True):
+def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True, tag="", fields=True):
     nbmax = max(s[3] for s in specs)
-    pk = run.read("batch_pk.bin", np.float64, (len(walkers), len(specs), nbmax))
-    xm = run.read("batch_xhi.bin", np.float64, (len(walkers), len(specs)))
+    pk = run.read(f"batch{tag}_pk.bin", np.float64, (len(walkers), len(specs), nbmax))
+    xm = run.read(f"batch{tag}_xhi.bin", np.float64, (len(walkers), len(specs)))
     for bi, (n, box, z, nb) in enumerate(specs):
         dt = boxes[bi].dtype
         shared = oracle.shared_radii(n, box, PHYS)
@@ -32,7 +32,7 @@ def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True):
             np.testing.assert_allclose(pk[wi, bi, :nb][ok], ev.pk[ok], rtol=tol_pk, atol=tol_pk * scale)
             assert np.all(pk[wi, bi, nb:] == 0)
             assert xm[wi, bi] == pytest.approx(ev.xhi_mean, abs=max(tol_pk, 1e-12))
-            if wi == 1:
+            if wi == 1 and fields:
                 x = run.read(f"mat_b{bi}_w1_xhi.bin", dt, (n, n, n))
                 assert np.mean((x == 0) != ev.flagged) <= flips_max
         if plain:
@@ -69,7 +69,11 @@ def _run(storage, specs, walkers, max_walkers, dtype, extra=()):
     return run, boxes
 
 
-def test_emu_f64_two_geometries_chunked():
+@pytest.mark.parametrize("radius_batch", [None, "3"])
+def test_emu_f64_two_geometries_chunked(monkeypatch, radius_batch):
+    # radius_batch: smoothed boxes per launch (default: all radii of a box at once)
+    if radius_batch:
+        monkeypatch.setenv("XS21_RADIUS_BATCH", radius_batch)
     specs = [(8, 6.0, 9.0, 3), (16, 12.0, 8.0, 4)]   # cell 0.75 Mpc: M_min can exceed the cell mass
     run, boxes = _run("f64", specs, EDGE, 2, np.float64, extra=("smoothed 1 3", "smoothed 1 0"))
     _check(run, boxes, specs, EDGE, 1e-11, 0.0)
@@ -112,3 +116,58 @@ def test_emu_rejects_bad_box():
     run.box(np.zeros((12, 12, 12), dtype=np.float32), 10.0, 9.0, 3)
     with pytest.raises(RuntimeError, match="power of two"):
         run.run()
+
+
+def test_emu_power_spectrum_n64_random_field():
+    # N = 64: the y pass splits into full aligned tiles plus gathered Nyquist
+    # columns, and the binning pass into main and rest tiles
+    n, box, nb = 64, 100.0, 8
+    rng = np.random.default_rng(64)
+    f = rng.standard_normal((n, n, n))
+    run = eh.EmuRun(storage="f64", max_walkers=1, phys={"pk_amp": AMP})
+    run.box(np.zeros((n, n, n)), box, 9.0, nb)
+    path = run.write_array("field.bin", f)
+    run.cmd("prepare")
+    run.cmd(f"pk 0 {path}")
+    run.run(timeout=1800)
+    pk = run.read("fpk_b0.bin", np.float64)[:nb]
+    ref, _, _, _ = oracle.power_spectrum(f, box, nb)
+    np.testing.assert_allclose(pk, ref, rtol=1e-12)
+
+
+def test_emu_resmooth_between_batches():
+    # A new density box re-smoothed between two batches (and an in-place
+    # re-smoothing) must reach the next batch; with max_walkers = 2 a batch of
+    # 5 walkers on 2 boxes runs as 6 (box, walker group) units through the
+    # shared scratch.  The emulated runtime defers all device work until the
+    # host synchronises, so reading results before the work is ordered fails.
+    specs = [(8, 6.0, 9.0, 3), (16, 12.0, 8.0, 4)]
+    walkers = EDGE[:5]
+    run = eh.EmuRun(storage="f64", max_walkers=2, phys={"pk_amp": AMP})
+    boxes = []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=70 + i, amp=AMP, dtype=np.float64)
+        boxes.append(d)
+        run.box(d, box, z, nb)
+    for w in walkers:
+        run.walker(*w)
+    new1 = synth.make_box(16, 12.0, 8.0, seed=99, amp=AMP, dtype=np.float64)
+    path = run.write_array("new1.bin", new1)
+    nbmax = max(s[3] for s in specs)
+    run.cmd("prepare")
+    run.cmd(f"batch {nbmax} A")
+    run.cmd(f"resmooth 1 {path}")
+    run.cmd(f"batch {nbmax} B")
+    run.cmd("resmooth 0 -")
+    run.cmd("resmooth 1 -")
+    run.cmd(f"batch {nbmax} C")
+    run.cmd("smoothed 1 2")
+    run.run()
+    _check(run, boxes, specs, walkers, 1e-11, 0.0, plain=False, tag="A", fields=False)
+    _check(run, [boxes[0], new1], specs, walkers, 1e-11, 0.0, plain=False, tag="B", fields=False)
+    for name in ("pk", "xhi"):
+        np.testing.assert_array_equal(run.read(f"batchB_{name}.bin", np.float64),
+                                      run.read(f"batchC_{name}.bin", np.float64))
+    shared = oracle.shared_radii(16, 12.0, PHYS)
+    got = run.read("sm_b1_j2.bin", np.float64, (16, 16, 16))
+    np.testing.assert_allclose(got, oracle.smooth(np.fft.rfftn(new1), 16, 12.0, shared[2]), atol=1e-13)

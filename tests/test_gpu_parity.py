@@ -288,3 +288,50 @@ def test_uneven_bf16_storage(xs):
         flips, rel = report(f"uneven-bf16 box{bi}", x.cpu().numpy(), ev, pk[2, bi], xhi[2, bi])
         assert flips <= 2e-2 and rel <= 5e-2
     ctx.close()
+
+
+def test_large_512_box(xs):
+    """512^3, 400 Mpc (the large workload's geometry): grid limits and FFT length 512.
+
+    Checks a plane wave through the estimator (closed form), one smoothed box
+    against the oracle, batched == plain on a sampled walker, and a walker
+    group of 64 on one z = 9 box.  The full 1024-walker x 3-box run is a
+    benchmark case, not a test.
+    """
+    import torch
+    n, box, z, nb = 512, 400.0, 9.0, 15
+    d = synth.make_box(n, box, z, seed=synth.BOX_SEEDS[(512, 400.0)], amp=AMP, dtype=np.float32)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f32", max_walkers=64, max_plain_radii=40)
+    # plane wave: closed-form P in one bin
+    g = np.indices((n, n, n), dtype=np.float32)
+    m = (3, -5, 7)
+    f = (1.3 * np.cos(2 * np.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n)).astype(np.float32)
+    del g
+    pk = ctx.power_spectrum(b, torch.from_numpy(f).cuda())
+    _, counts = ctx.bins(b)
+    bi = oracle.bin_of_n2(sum(v * v for v in m), n, nb)
+    expect = np.zeros(nb)
+    expect[bi] = 1.3 ** 2 * box ** 3 / (2 * counts[bi])
+    np.testing.assert_allclose(pk, expect, rtol=2e-5, atol=2e-5 * expect.max())
+    del f
+    # one smoothed box (R = 5 Mpc neighbourhood of the ladder) against the oracle
+    radii = ctx.radii(b)
+    j = min(range(len(radii)), key=lambda i: abs(radii[i] - 5.0))
+    got = ctx.smoothed(b, j).cpu().numpy().astype(np.float64)
+    ref = oracle.smooth(np.fft.rfftn(d.astype(np.float64)), n, box, radii[j])
+    err = float(np.abs(got - ref).max() / np.abs(d).max())
+    print(f"[large-512] smoothed R={radii[j]:.3f}: max err / max|delta| = {err:.2e}", flush=True)
+    assert err <= 2e-6
+    del got, ref
+    walkers = synth.draw_walkers(64, synth.WALKER_SEEDS["large-512"])
+    pk, xhi = ctx.eval_batch([b], walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    assert np.isfinite(pk).all() and np.all((xhi >= 0) & (xhi <= 1))
+    w = walkers[5]
+    out = ctx.eval(b, w, radii=oracle.walker_radii(radii, w[1]), fields=False)
+    np.testing.assert_allclose(out["pk"], pk[5, 0], rtol=1e-6)
+    assert out["xhi_mean"] == pytest.approx(xhi[5, 0], abs=1e-6)
+    ctx.close()
