@@ -257,21 +257,25 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
   return L;
 }
 
-// Walker constants and its thresholds padded to thr_stride() entries: +inf
-// before the walker's first radius (plain lists start at 0) and past the end.
+// Walker constants and its thresholds in radius slots s = nr - 1 - j (slot 0
+// is the cell radius, the last ladder entry), padded to thr_stride() slots:
+// +inf for radii above the walker's R_mfp (plain lists use every radius) and
+// past the ladder end.  The kernel tests the slots in groups of 8 up to the
+// last group holding a used slot.
 template <typename T>
 void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned char* wc_dst, T* thr_dst,
                        double zeta) {
+  const int nr = static_cast<int>(wp.thr.size());
+  const int used = plain ? nr : nr - wp.first;
   WalkerConst<T> c;
   c.zeta = static_cast<T>(zeta);
   c.a_cell = static_cast<T>(wp.a_cell);
-  c.first = plain ? 0 : wp.first;
+  c.chunks = (used + 7) / 8;
   c.partial = wp.partial ? 1 : 0;
   std::memcpy(wc_dst, &c, sizeof c);
   const T inf = std::numeric_limits<T>::infinity();
-  const int nr = static_cast<int>(wp.thr.size());
-  for (int j = 0; j < xs21::thr_stride(); ++j)
-    thr_dst[j] = (j < c.first || j >= nr) ? inf : static_cast<T>(wp.thr[j]);
+  for (int s = 0; s < xs21::thr_stride(); ++s)
+    thr_dst[s] = s < used ? static_cast<T>(wp.thr[nr - 1 - s]) : inf;
 }
 
 // Writes the constants + thresholds of `walkers` for box b into host memory
@@ -417,7 +421,7 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
-  const long tiles = xs21::bins_tiles(b.n);
+  const long parts = xs21::bins_parts(b.n, count);
   const void* tw = tw_ptr(c, b.dtype);
   hipError_t e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
     return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, count * n, hp, h, nullptr, 1, 0, 0, tw, kNtab,
@@ -432,9 +436,9 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   if (e != hipSuccess) return e;
   const double L3 = b.box * b.box * b.box;
   const double n6 = std::pow(static_cast<double>(n), 6);
-  const double pbytes = static_cast<double>(count) * (tiles * b.nbins + xs21::ion_grid(b.n)) * 8;
+  const double pbytes = static_cast<double>(count) * (parts * b.nbins + xs21::ion_grid(b.n)) * 8;
   return timed(c, st, XS21_K_FINALIZE, pbytes, [&] {
-    return xs21::launch_finalize(count, sl.part, tiles, b.nbins, sl.xpart, xs21::ion_grid(b.n),
+    return xs21::launch_finalize(count, sl.part, parts, b.nbins, sl.xpart, xs21::ion_grid(b.n),
                                  reinterpret_cast<const double*>(c->ws + b.off_counts), L3 / n6, 1.0 / cells, pk,
                                  pk_stride, nbins_out, xhi, xhi_stride, st);
   });
@@ -839,7 +843,7 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   const BoxRec& b = ctx->boxes[box];
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   unsigned char* s = ctx->ws + ctx->lay.scratch;
-  const long tiles = xs21::bins_tiles(b.n);
+  const long parts = xs21::bins_parts(b.n, 1);
   double* part = reinterpret_cast<double*>(s + align_up(b.spec_bytes()));
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, s, n * n, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
@@ -848,7 +852,7 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
                                        b.nbins, part, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;
-  HIPCHECK(ctx, xs21::launch_finalize(1, part, tiles, b.nbins, nullptr, 0,
+  HIPCHECK(ctx, xs21::launch_finalize(1, part, parts, b.nbins, nullptr, 0,
                                       reinterpret_cast<const double*>(ctx->ws + b.off_counts),
                                       L3 / std::pow(static_cast<double>(n), 6), 1.0, outs, b.nbins, b.nbins, nullptr,
                                       0, ctx->stream));

@@ -58,7 +58,7 @@ template <typename T>
 struct WalkerConst {
   T zeta;      // ionising efficiency
   T a_cell;    // 1 / sqrt(2 (sigma^2(M_min) - sigma^2(R_cell))), valid if partial != 0
-  int32_t first;    // first radius index the walker filters at (R <= R_mfp)
+  int32_t chunks;   // radius slots tested, in groups of 8 (slots run from the cell radius up)
   int32_t partial;  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged
 };
 

@@ -342,9 +342,11 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 // and keep 128-byte aligned loads: "main" tiles are 16 consecutive kx < KM of
 // one y (KM = the largest multiple of 16 <= N/2), "rest" tiles gather the
 // remaining columns (kx in [KM, N/2], the Nyquist plane for N >= 32) of 16
-// consecutive (y, kx) pairs.  Each block writes FP64 bin sums of w |X|^2 for
-// its tile to part[outer][tile][nbins].  Weights w: 1 on the kx = 0 and
-// kx = N/2 planes, 2 elsewhere (half spectrum).
+// consecutive (y, kx) pairs.  Block i of a spectrum's `parts` blocks takes
+// tiles i, i + parts, i + 2 parts, ... (so that blocks running together read
+// neighbouring tiles), accumulates its bin sums over them and writes FP64
+// sums of w |X|^2 for bins [b0, b0 + nbc) to part[spectrum][i][nbins].
+// Weights w: 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere (half spectrum).
 // ---------------------------------------------------------------------------
 template <int N, int TI>
 struct BinTiles {
@@ -372,8 +374,9 @@ struct BinTiles {
 };
 
 template <typename T, int N>
-__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src, long nitems,
-                                                                const int8_t* __restrict__ bintab, int nbins,
+__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src, long parts,
+                                                                const int8_t* __restrict__ bintab,
+                                                                int nbins, int b0, int nbc,
                                                                 double* __restrict__ part,
                                                                 const cplx<T>* __restrict__ tw, int tstride) {
   using A = AxisShape<N>;
@@ -386,122 +389,113 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
   constexpr int NSTEP = A::NT / A::TI;
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
+  // slot[b][t]: thread t's running sum of bin b0 + b (nbc x NT values of T)
+  HIP_DYNAMIC_SHARED(unsigned char, dyn_lds)
+  T* slot = reinterpret_cast<T*>(dyn_lds);
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int cc = t % A::TI, j = t / A::TI;  // loads: rows j + k NSTEP; FFT: team member j of column cc
+  const long spec = blockIdx.x / parts, first = blockIdx.x % parts;
+  const cplx<T>* sp = src + spec * N * PLANE;
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
-  // item g = spectrum * COUNT + tile; its column for this thread (ky < 0: none)
+  for (int b = 0; b < nbc; ++b) slot[b * A::NT + t] = T(0);  // own column only
   cplx<T> pre[L];
-  const auto load = [&](long g) {
+  const auto load = [&](long tile) {
     int ky, kx;
-    BT::column(g % BT::COUNT, cc, ky, kx);
+    BT::column(tile, cc, ky, kx);
     const bool live = ky >= 0;
-    const long off = (g / BT::COUNT) * N * PLANE + static_cast<long>(j) * PLANE +
-                     static_cast<long>(live ? ky : 0) * HP + kx;  // a valid address either way
+    const long off = static_cast<long>(j) * PLANE + static_cast<long>(live ? ky : 0) * HP + kx;  // valid either way
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-      const cplx<T> v = src[off + static_cast<long>(k) * NSTEP * PLANE];
+      const cplx<T> v = sp[off + static_cast<long>(k) * NSTEP * PLANE];
       pre[k] = live ? v : cplx<T>{T(0), T(0)};
     }
   };
-  long g = blockIdx.x;
-  if (g < nitems) load(g);
-  for (; g < nitems; g += gridDim.x) {
+  if (first < BT::COUNT) load(first);
+  for (long tile = first; tile < BT::COUNT; tile += parts) {
 #pragma unroll
     for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
     __syncthreads();
-    if (g + gridDim.x < nitems) load(g + gridDim.x);
+    if (tile + parts < BT::COUNT) load(tile + parts);
     fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
-
-    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1
-    int bin[M];
-    T val[M];
-    {
-      int ky, kx;
-      BT::column(g % BT::COUNT, cc, ky, kx);
-      const int ny = ky < N / 2 ? ky : ky - N;
-      const int cyx = ny * ny + kx * kx;
-      const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
-      const bool col = ky >= 0;
+    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1; |nz| is
+    // monotone there, so equal bins come in runs, each added to the thread's
+    // own slot column once
+    int ky, kx;
+    BT::column(tile, cc, ky, kx);
+    const int ny = ky < N / 2 ? ky : ky - N;
+    const int cyx = ny * ny + kx * kx;
+    const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
+    int cur = -1;
+    T run = T(0);
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int kz = j * M + m;
-        const int nz = kz < N / 2 ? kz : kz - N;
-        const cplx<T> x = lds[kz * A::TI + cc];
-        bin[m] = col ? bintab[nz * nz + cyx] : -1;
-        val[m] = w * (x.x * x.x + x.y * x.y);
+    for (int m = 0; m < M; ++m) {
+      const int kz = j * M + m;
+      const int nz = kz < N / 2 ? kz : kz - N;
+      const cplx<T> x = lds[kz * A::TI + cc];
+      const int bin = ky >= 0 ? bintab[nz * nz + cyx] - b0 : -1;
+      const int bb = (bin >= 0 && bin < nbc) ? bin : -1;
+      if (bb != cur) {
+        if (cur >= 0) slot[cur * A::NT + t] += run;
+        run = T(0);
+        cur = bb;
       }
+      run += w * (x.x * x.x + x.y * x.y);
     }
-    // Bin sums through LDS (the FFT buffer, reused): each thread adds the runs
-    // of equal bins along its kz range (|nz| is monotone there, so a run is
-    // rarely broken) into its own column of slot[bin][thread], then one wave
-    // per bin sums the NT columns in a fixed order (deterministic).
-    constexpr int CAP = 2 * N * A::TI / A::NT;  // bins per chunk: T values in the FFT buffer per thread
-    T* slot = reinterpret_cast<T*>(lds);
-    for (int b0 = 0; b0 < nbins; b0 += CAP) {
-      const int nb = min(CAP, nbins - b0);
-      __syncthreads();  // the FFT buffer (or the previous chunk) is no longer read
-      for (int b = 0; b < nb; ++b) slot[b * A::NT + t] = T(0);
-      int cur = -1;
-      T run = T(0);
+    if (cur >= 0) slot[cur * A::NT + t] += run;
+    __syncthreads();  // the FFT buffer is read before the next tile is stored
+  }
+  // one wave per bin sums the NT slot columns in a fixed order (deterministic)
+  double* out = part + (spec * parts + blockIdx.x % parts) * nbins + b0;
+  for (int b = wave; b < nbc; b += NW) {
+    T sum = T(0);
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        if (bin[m] != cur) {
-          if (cur >= b0 && cur < b0 + nb) slot[(cur - b0) * A::NT + t] += run;
-          run = T(0);
-          cur = bin[m];
-        }
-        run += val[m];
-      }
-      if (cur >= b0 && cur < b0 + nb) slot[(cur - b0) * A::NT + t] += run;
-      __syncthreads();
-      for (int b = wave; b < nb; b += NW) {
-        T sum = T(0);
-#pragma unroll
-        for (int i = 0; i < A::NT / 64; ++i) sum += slot[b * A::NT + i * 64 + lane];
-        const double d = wave_sum(static_cast<double>(sum));
-        if (lane == 0) part[g * nbins + b0 + b] = d;
-      }
-    }
-    __syncthreads();  // slots are read before the next tile is stored
+    for (int i = 0; i < A::NT / 64; ++i) sum += slot[b * A::NT + i * 64 + lane];
+    const double d = wave_sum(static_cast<double>(sum));
+    if (lane == 0) out[b] = d;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Per-cell ionisation (Section 2.1, eq. 1 and partial ionisation).
-// d[j] = delta_R at radius j of the ladder (decreasing R), cell = delta at the
-// cell radius.  Flag iff delta_R >= thr[j] for some j: thresholds are the
-// FP64-planned exact rewrite of zeta f_coll >= 1, padded with +inf to kNrMax
-// entries (radii above the walker's R_mfp and past the ladder end), so the
-// test is branch-free and its uniform threshold loads batch into wide scalar
+// Radius slots run from the cell radius up: d[s] = delta_R at ladder radius
+// nr - 1 - s, so slot 0 is the cell radius and a walker uses the slots below
+// its count of radii with R <= R_mfp.  Flag iff delta_R >= thr[s] for some
+// slot: thresholds are the FP64-planned exact rewrite of zeta f_coll >= 1,
+// +inf for slots the walker does not use, tested 8 slots at a time up to the
+// walker's last used group (a wave-uniform exit), so the compares follow the
+// walker's own radius count and its threshold loads batch into wide scalar
 // loads.  Unflagged cells keep x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)).
 // ---------------------------------------------------------------------------
 template <typename T, int NR>
-__device__ __forceinline__ T cell_xhi(const T (&d)[NR], T cell, const WalkerConst<T>& c, const T* thr_w, T dc) {
-  // OR over radii as wave-wide lane masks: one compare into a scalar mask per
-  // radius; thresholds of radii the walker does not use are +inf
+__device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, T dc) {
+  static_assert(NR % 8 == 0, "radius slots come in groups of 8");
+  // OR over radii as wave-wide lane masks: one compare into a scalar mask per slot
   unsigned long long m = 0;
 #pragma unroll
-  for (int j = 0; j < NR; ++j) m |= __ballot(d[j] >= thr_w[j]);
+  for (int g = 0; g < NR / 8; ++g) {
+    if (g >= c.chunks) break;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m |= __ballot(d[8 * g + k] >= thr_w[8 * g + k]);
+  }
   const bool flag = (m >> __lane_id()) & 1ull;
   T x = T(1);
   if (flag) {
     x = T(0);
   } else if (c.partial) {
-    x = T(1) - c.zeta * erfc_t(c.a_cell * (dc - cell));
+    x = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
   }
   return x;
 }
 
-// Loads delta_R of one cell for every radius slot.  Slots past the ladder end
-// repeat the last radius (their thresholds are +inf, so they never flag), so
-// that all loads are unconditional and issue back to back.
+// Loads delta_R of one cell for every radius slot (slot s = ladder radius
+// nr - 1 - s).  Slots past the ladder end repeat the largest radius (their
+// thresholds are +inf), so that all loads are unconditional and issue back to
+// back.
 template <typename T, typename S, int NR>
-__device__ __forceinline__ void load_radii(const S* __restrict__ dR, size_t n3, size_t cell, int nr, T (&d)[NR],
-                                           T& dcell) {
+__device__ __forceinline__ void load_radii(const S* __restrict__ dR, size_t n3, size_t cell, int nr, T (&d)[NR]) {
 #pragma unroll
-  for (int j = 0; j < NR; ++j) d[j] = load_as<T>(dR, static_cast<size_t>(j < nr ? j : nr - 1) * n3 + cell);
-  dcell = load_as<T>(dR, static_cast<size_t>(nr - 1) * n3 + cell);
+  for (int s = 0; s < NR; ++s) d[s] = load_as<T>(dR, static_cast<size_t>(s < nr ? nr - 1 - s : 0) * n3 + cell);
 }
 
 // Threads and LDS batches of the ionisation pass: one cell per thread over a
@@ -570,15 +564,14 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
     const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
     T d[kNrMax];
-    T dcell;
-    load_radii<T, S>(dR, N3, cell, nr, d, dcell);
+    load_radii<T, S>(dR, N3, cell, nr, d);
     const T od = T(1) + delta[cell];
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        const T xh = cell_xhi<T, kNrMax>(d, dcell, wc[w], thr + static_cast<size_t>(w) * kNrMax, dc);
+        const T xh = cell_xhi<T, kNrMax>(d, wc[w], thr + static_cast<size_t>(w) * kNrMax, dc);
         ldsr[2 * (q * N + x) + row] = tb * xh * od;
         if constexpr (IS::NT >= 64) {
           const T s = row_sum(xh);
@@ -622,9 +615,8 @@ __global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, c
   for (size_t cell = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; cell < N3;
        cell += static_cast<size_t>(gridDim.x) * 256) {
     T d[kNrMax];
-    T dcell;
-    load_radii<T, S>(dR, N3, cell, nr, d, dcell);
-    const T x = cell_xhi<T, kNrMax>(d, dcell, c, thr, dc);
+    load_radii<T, S>(dR, N3, cell, nr, d);
+    const T x = cell_xhi<T, kNrMax>(d, c, thr, dc);
     if (xhi) xhi[cell] = x;
     if (dtb) dtb[cell] = tb * x * (T(1) + delta[cell]);
   }
@@ -733,6 +725,30 @@ int axis_tile(int n) {
 long axis_tiles(int n, long inner) {
   const int ti = axis_tile(n);
   return ti > 0 ? (inner + ti - 1) / ti : 0;
+}
+
+// Blocks per spectrum of the binning pass: enough blocks over `outer`
+// spectra to fill the chip, each walking every parts-th tile.
+long bins_parts(int n, long outer) {
+  const long count = bins_tiles(n);
+  const long k = (kPipeBlocks + outer - 1) / outer;
+  return k < 1 ? 1 : (k > count ? count : k);
+}
+
+// Bins per launch of the binning pass: its slot array (bins x threads) and
+// its static LDS stay within 128 KB per block where they can; at least one
+// bin (FP64 at N = 512 then uses 144 KB of the CU's 160 KB).  (The CPU
+// emulation used by the tests lowers the budget so that FP64 at N = 16 takes
+// several launches.)
+#ifndef XS21_BINS_LDS_BUDGET
+#define XS21_BINS_LDS_BUDGET 131072
+#endif
+template <typename T, int N>
+constexpr int bins_per_launch() {
+  using A = AxisShape<N>;
+  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
+  constexpr long per = (XS21_BINS_LDS_BUDGET - stat) / (static_cast<long>(A::NT) * static_cast<long>(sizeof(T)));
+  return per < 1 ? 1 : static_cast<int>(per);
 }
 
 long bins_tiles(int n) {
@@ -851,16 +867,22 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
 hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const int8_t* bintab, int nbins,
                             double* part, const void* tw, int ntab, hipStream_t s) {
   if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535) return hipErrorInvalidValue;
+  const long parts = bins_parts(n, outer);
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
       constexpr int N = decltype(nc)::value;
       using A = AxisShape<N>;
-      const long items = BinTiles<N, A::TI>::COUNT * outer;
-      hipLaunchKernelGGL((k_axis_bins<T, N>), dim3(grid_for(items, kPipeBlocks)), dim3(A::NT), 0, s,
-                         static_cast<const cplx<T>*>(src), items, bintab, nbins, part,
-                         static_cast<const cplx<T>*>(tw), ntab / N);
-      return hipGetLastError();
+      constexpr int per = bins_per_launch<T, N>();
+      hipError_t e = hipSuccess;
+      for (int b0 = 0; b0 < nbins && e == hipSuccess; b0 += per) {
+        const int nbc = nbins - b0 < per ? nbins - b0 : per;
+        hipLaunchKernelGGL((k_axis_bins<T, N>), dim3(static_cast<unsigned>(outer * parts)), dim3(A::NT),
+                           static_cast<size_t>(nbc) * A::NT * sizeof(T), s, static_cast<const cplx<T>*>(src), parts,
+                           bintab, nbins, b0, nbc, part, static_cast<const cplx<T>*>(tw), ntab / N);
+        e = hipGetLastError();
+      }
+      return e;
     });
   });
 }

@@ -14,7 +14,8 @@ constexpr int kBF16 = 2;
 
 int axis_tile(int n);                   // inner columns per block of the strided passes
 long axis_tiles(int n, long inner);     // blocks along the inner dimension
-long bins_tiles(int n);                 // blocks per spectrum of the binning z pass
+long bins_tiles(int n);                 // column tiles per spectrum of the binning z pass
+long bins_parts(int n, long outer);     // partial sums per spectrum written by the binning pass
 int ion_grid(int n);                    // blocks of the ionisation pass
 int max_group();                        // walkers per ionisation launch
 int max_radii();                        // radii per ladder

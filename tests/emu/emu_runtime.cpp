@@ -17,6 +17,7 @@ namespace hipemu {
 thread_local idx3 tl_thread{0, 0, 0};
 thread_local idx3 tl_block{0, 0, 0};
 dim3 g_grid, g_block;
+unsigned char* g_dyn_shared = nullptr;
 
 namespace {
 struct Wave {

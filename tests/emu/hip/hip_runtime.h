@@ -67,9 +67,12 @@ int lane_id();
 unsigned long long wave_ballot(bool pred);
 int wave_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
 void run_grid(dim3 grid, dim3 block, void (*body)(void*), void* arg);
+extern unsigned char* g_dyn_shared;  // dynamic LDS of the running launch
 void enqueue(hipStream_t s, std::function<void()> op);
 hipError_t last_error(hipError_t set = -1);
 }  // namespace hipemu
+
+#define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(::hipemu::g_dyn_shared);
 
 #define threadIdx (::hipemu::tl_thread)
 #define blockIdx (::hipemu::tl_block)
@@ -120,13 +123,20 @@ struct Launch {
 };
 
 template <typename... KArgs, typename... Args>
-inline hipError_t launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t, hipStream_t stream, Args&&... args) {
+inline hipError_t launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t stream,
+                         Args&&... args) {
   if (block.x * block.y * block.z > 1024 || block.y != 1 || block.z != 1 || grid.x == 0 || grid.y == 0 || grid.z == 0)
     return last_error(hipErrorInvalidValue);
   using Tup = std::tuple<KArgs...>;
   using L = Launch<void (*)(KArgs...), Tup>;
   auto l = std::make_shared<L>(L{k, Tup(static_cast<KArgs>(args)...)});
-  enqueue(stream, [l, grid, block] { run_grid(grid, block, &L::body, l.get()); });
+  enqueue(stream, [l, grid, block, shmem] {
+    // exactly `shmem` bytes, so that AddressSanitizer sees overruns
+    std::unique_ptr<unsigned char[]> dyn(shmem ? new unsigned char[shmem] : nullptr);
+    g_dyn_shared = dyn.get();
+    run_grid(grid, block, &L::body, l.get());
+    g_dyn_shared = nullptr;
+  });
   return hipSuccess;
 }
 }  // namespace hipemu

@@ -36,9 +36,10 @@ def build() -> str:
     if not _stale():
         return BIN
     os.makedirs(os.path.dirname(BIN), exist_ok=True)
-    # XS21_PIPE_BLOCKS=3: grid-stride kernels run 3 blocks, each over many items
+    # XS21_PIPE_BLOCKS=3: grid-stride kernels run 3 blocks, each over many
+    # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 2 bins per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
-           "-DXS21_PIPE_BLOCKS=3",
+           "-DXS21_PIPE_BLOCKS=3", "-DXS21_BINS_LDS_BUDGET=17664",
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], "-x", "none", *SRC[1:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
