@@ -24,6 +24,29 @@ __host__ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
 
+// Streaming (non-temporal) global stores and loads of complex values, for
+// data touched once per pass: the cache lines are not kept for reuse.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((vector_size(8)));
+};
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((vector_size(16)));
+};
+template <typename T>
+__device__ __forceinline__ void store_stream(cplx<T>* p, cplx<T> v) {
+  const typename Pair<T>::type w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<typename Pair<T>::type*>(p));
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> load_stream(const cplx<T>* p) {
+  const typename Pair<T>::type w = __builtin_nontemporal_load(reinterpret_cast<const typename Pair<T>::type*>(p));
+  return {w[0], w[1]};
+}
+
 // bf16 stored as raw 16-bit patterns (upper half of an IEEE binary32).
 struct bf16 {
   uint16_t bits;
@@ -52,6 +75,13 @@ template <typename S, typename T>
 __host__ __device__ __forceinline__ void store_as(S* p, size_t i, T v) { p[i] = static_cast<S>(v); }
 template <>
 __host__ __device__ __forceinline__ void store_as<bf16, float>(bf16* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
+// Same, as a streaming store (FP32 / FP64; BF16 pairs are stored plainly).
+template <typename S, typename T>
+__device__ __forceinline__ void store_as_stream(S* p, size_t i, T v) {
+  __builtin_nontemporal_store(static_cast<S>(v), p + i);
+}
+template <>
+__device__ __forceinline__ void store_as_stream<bf16, float>(bf16* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
 
 // Per-(walker, box) constants consumed by the per-cell ionisation pass.
 template <typename T>

@@ -127,8 +127,8 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restric
 // for a batch of smoothing radii.  Items g = radius * groups + group of WB row
 // pairs form a grid-stride loop; the loads of a block's next item are issued
 // into registers before the FFT and stores of the current one.  Radius r reads
-// in + r istride, writes out + r ostride and only reads entries kx <= kmax(r)
-// (the rest are zero after its sharp-k cut).
+// in + r istride, writes out + r ostride (streaming stores) and only reads
+// entries kx <= kmax(r) (the rest are zero after its sharp-k cut).
 // ---------------------------------------------------------------------------
 template <typename T, typename ST, int N>
 __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __restrict__ in, ST* __restrict__ out,
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
       const long p = p0 + q;
       if (p < npairs) {
         const cplx<T> v = lds[q * N + t];
-        store_as(dst, (2 * p) * N + t, v.x * scale);
-        store_as(dst, (2 * p + 1) * N + t, v.y * scale);
+        store_as_stream(dst, (2 * p) * N + t, v.x * scale);
+        store_as_stream(dst, (2 * p + 1) * N + t, v.y * scale);
       }
     }
     __syncthreads();
@@ -295,6 +295,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
 // as a grid-stride loop over tiles g = slice * tiles_x + column block: each
 // block issues the global loads of its next tile into registers before the
 // FFT of the current one, so that memory latency overlaps the transform.
+// Loads and stores are streaming: each element is touched once per pass.
 template <typename T, int N, int DIR>
 __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* src, cplx<T>* dst, long inner,
                                                                 long tiles_x, long ntiles,
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
   if (g < ntiles) {
     const long off = offset(g);
 #pragma unroll
-    for (int k = 0; k < L; ++k) pre[k] = src[off + static_cast<long>(k) * NSTEP * inner];
+    for (int k = 0; k < L; ++k) pre[k] = load_stream(src + off + static_cast<long>(k) * NSTEP * inner);
   }
   for (; g < ntiles; g += gridDim.x) {
 #pragma unroll
@@ -327,11 +328,11 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
     if (gn < ntiles) {
       const long offn = offset(gn);
 #pragma unroll
-      for (int k = 0; k < L; ++k) pre[k] = src[offn + static_cast<long>(k) * NSTEP * inner];
+      for (int k = 0; k < L; ++k) pre[k] = load_stream(src + offn + static_cast<long>(k) * NSTEP * inner);
     }
     fft_team<N, DIR, T, typename A::Plan>(lds + c, A::TI, n0, twl, 1);
 #pragma unroll
-    for (int k = 0; k < L; ++k) dst[off + static_cast<long>(k) * NSTEP * inner] = lds[t + k * A::NT];
+    for (int k = 0; k < L; ++k) store_stream(dst + off + static_cast<long>(k) * NSTEP * inner, lds[t + k * A::NT]);
     __syncthreads();
   }
 }
@@ -399,6 +400,16 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
   const cplx<T>* sp = src + spec * N * PLANE;
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
   for (int b = 0; b < nbc; ++b) slot[b * A::NT + t] = T(0);  // own column only
+  // Bins of |n|^2 <= (N/2)^2 (larger |n| are never binned), staged in LDS up to
+  // N = 256 (16 KB); visible after the first barrier of the tile loop.
+  constexpr int NB2 = (N / 2) * (N / 2) + 1;
+  constexpr bool kLdsBins = N <= 256;
+  __shared__ int btab_w[kLdsBins ? (NB2 + 3) / 4 : 1];
+  const int8_t* btab = reinterpret_cast<const int8_t*>(btab_w);
+  if constexpr (kLdsBins) {
+    const int* src_w = reinterpret_cast<const int*>(bintab);  // the table holds 3 (N/2)^2 + 1 bytes
+    for (int i = t; i < (NB2 + 3) / 4; i += A::NT) btab_w[i] = src_w[i];
+  }
   cplx<T> pre[L];
   const auto load = [&](long tile) {
     int ky, kx;
@@ -433,7 +444,9 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
       const int kz = j * M + m;
       const int nz = kz < N / 2 ? kz : kz - N;
       const cplx<T> x = lds[kz * A::TI + cc];
-      const int bin = ky >= 0 ? bintab[nz * nz + cyx] - b0 : -1;
+      const int n2 = nz * nz + cyx;
+      int bin = -1;
+      if (ky >= 0 && n2 < NB2) bin = (kLdsBins ? btab[n2] : bintab[n2]) - b0;
       const int bb = (bin >= 0 && bin < nbc) ? bin : -1;
       if (bb != cur) {
         if (cur >= 0) slot[cur * A::NT + t] += run;
@@ -539,8 +552,8 @@ struct IonShape {
 // owns cell (row 2p + t / N, x = t % N).  The smoothed values of its cell stay
 // in registers while every walker of the group is processed, so the resident
 // smoothed boxes are read once per group.  Two real rows are transformed as
-// one complex row.  Output: spec[w][row][kx] for w < nw, and per-block x_HI
-// sums xpart[w][block].
+// one complex row.  Output: spec[w][row][kx] for w < nw (streaming stores),
+// and per-block x_HI sums xpart[w][block].
 template <typename T, typename S, int N>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ delta, int nr, const WalkerConst<T>* __restrict__ wc,
@@ -594,8 +607,8 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
           cplx<T> A, B;
           unpack_pair<N>(lds + q * N, k, A, B);
           cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
-          o[k] = A;
-          o[IS::HP + k] = B;
+          store_stream(o + k, A);
+          store_stream(o + IS::HP + k, B);
         }
       }
       __syncthreads();
@@ -746,7 +759,8 @@ long bins_parts(int n, long outer) {
 template <typename T, int N>
 constexpr int bins_per_launch() {
   using A = AxisShape<N>;
-  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
+  constexpr long table = N <= 256 ? ((N / 2) * (N / 2) + 4) / 4 * 4 : 4;  // staged bin table
+  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>)) + table;
   constexpr long per = (XS21_BINS_LDS_BUDGET - stat) / (static_cast<long>(A::NT) * static_cast<long>(sizeof(T)));
   return per < 1 ? 1 : static_cast<int>(per);
 }

@@ -106,6 +106,10 @@ inline int __float_as_int(float f) { return __builtin_bit_cast(int, f); }
 inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
 inline float __fdividef(float a, float b) { return a / b; }
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
+template <typename V>
+inline void __builtin_nontemporal_store(V v, V* p) { *p = v; }
+template <typename V>
+inline V __builtin_nontemporal_load(const V* p) { return *p; }
 inline float __expf(float x) { return expf(x); }
 
 using std::max;
