@@ -202,10 +202,13 @@ int box_storage(const BoxRec& b, int storage) { return b.dtype == xs21::kF64 ? x
 // Smoothing: the box spectrum + one spectrum per radius of a launch batch.
 size_t smooth_scratch(const BoxRec& b) { return (1 + static_cast<size_t>(b.rbatch)) * align_up(b.spec_bytes()); }
 
-// Evaluation: walker spectra, bin partial sums, x_HI partial sums.
+// Evaluation: walker spectra, their Nyquist planes, bin partial sums, x_HI partial sums.
+size_t nyq_bytes(const BoxRec& b) { return static_cast<size_t>(b.n) * b.n * 2 * real_size(b.dtype); }
+
 size_t eval_scratch(const BoxRec& b, int group) {
   const long tiles = xs21::bins_tiles(b.n);
-  return align_up(group * b.spec_bytes()) + align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
+  return align_up(group * b.spec_bytes()) + align_up(group * nyq_bytes(b)) +
+         align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
          align_up(static_cast<size_t>(group) * xs21::ion_grid(b.n) * 8);
 }
 
@@ -306,7 +309,7 @@ hipError_t forward3d(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* r
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const void* tw = tw_ptr(c, b.dtype);
   hipError_t e = timed(c, st, XS21_K_ROWS_R2C, cells * rs + modes * 2 * rs, [&] {
-    return xs21::launch_rows_r2c(b.dtype, b.n, real_in, spec, n * n, tw, kNtab, st);
+    return xs21::launch_rows_r2c(b.dtype, b.n, real_in, spec, nullptr, n * n, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
   e = timed(c, st, XS21_K_AXIS_FWD, 2 * modes * 2 * rs, [&] {
@@ -377,10 +380,11 @@ hipError_t smooth_box(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
 }
 
 // Scratch of one evaluation of `count` walkers on one box: their x-transformed
-// spectra, then the binning pass's FP64 partial sums, then the ionisation
-// pass's x_HI partial sums.
+// spectra (kx < N/2), their Nyquist planes [y][z], then the binning pass's
+// FP64 partial sums, then the ionisation pass's x_HI partial sums.
 struct EvalSlot {
   void* spec;
+  void* nyq;
   double* part;
   double* xpart;
 };
@@ -388,7 +392,8 @@ struct EvalSlot {
 EvalSlot eval_slot(const BoxRec& b, unsigned char* base, int count) {
   EvalSlot s;
   s.spec = base;
-  s.part = reinterpret_cast<double*>(base + align_up(count * b.spec_bytes()));
+  s.nyq = base + align_up(count * b.spec_bytes());
+  s.part = reinterpret_cast<double*>(static_cast<unsigned char*>(s.nyq) + align_up(count * nyq_bytes(b)));
   s.xpart = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(s.part) +
                                       align_up(static_cast<size_t>(count) * xs21::bins_tiles(b.n) * b.nbins * 8));
   return s;
@@ -408,7 +413,7 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
       c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
       [&] {
         return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_delta, nr, wc, thr, count, tb,
-                                c->phys.delta_c, sl.spec, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
+                                c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
       },
       ion_ops);
 }
@@ -423,13 +428,18 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const long parts = xs21::bins_parts(b.n, count);
   const void* tw = tw_ptr(c, b.dtype);
-  hipError_t e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * modes * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, count * n, hp, h, nullptr, 1, 0, 0, tw, kNtab,
-                             st);
+  // y pass of the kx < N/2 columns, then of the Nyquist planes
+  hipError_t e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * n * n * (n / 2) * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, count * n, hp, n / 2, nullptr, 1, 0, 0, tw,
+                             kNtab, st);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * n * n * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.nyq, sl.nyq, count, n, n, nullptr, 1, 0, 0, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
   e = timed(c, st, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
-    return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, count,
+    return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, count,
                                   reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, sl.part, tw, kNtab,
                                   st);
   });
@@ -841,16 +851,21 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!field || !pk) return fail(XS21_EINVAL, "null argument");
   const BoxRec& b = ctx->boxes[box];
-  const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
-  unsigned char* s = ctx->ws + ctx->lay.scratch;
+  const long n = b.n, hp = static_cast<long>(b.pitch());
+  // same layout and passes as one walker's spectrum in an evaluation
+  const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, 1);
   const long parts = xs21::bins_parts(b.n, 1);
-  double* part = reinterpret_cast<double*>(s + align_up(b.spec_bytes()));
+  double* part = sl.part;
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
-  HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, s, n * n, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, s, s, n, hp, h, nullptr, 1, 0, 0, tw_ptr(ctx, b.dtype), kNtab,
+  const void* tw = tw_ptr(ctx, b.dtype);
+  HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, sl.spec, sl.nyq, n * n, tw, kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, n, hp, n / 2, nullptr, 1, 0, 0, tw, kNtab,
                                   ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, s, 1, reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab),
-                                       b.nbins, part, tw_ptr(ctx, b.dtype), kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, sl.nyq, sl.nyq, 1, n, n, nullptr, 1, 0, 0, tw, kNtab,
+                                  ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1,
+                                       reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.nbins, part, tw,
+                                       kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;
   HIPCHECK(ctx, xs21::launch_finalize(1, part, parts, b.nbins, nullptr, 0,
                                       reinterpret_cast<const double*>(ctx->ws + b.off_counts),

@@ -5,7 +5,10 @@
 //   half spectrum   [z][y][kx], kx in [0, N/2]      N * N * HP complex, rows padded
 //                   to HP = N/2 + 1 rounded up to 16 (128-byte aligned rows)
 //   smoothed boxes  [radius][z][y][x]               N_R * N^3 (storage type S)
-//   walker spectra  [walker][z][y][kx]
+//   walker spectra  [walker][z][y][kx], kx < N/2, rows padded to HP as above,
+//                   with the Nyquist plane kx = N/2 apart as [walker][y][z]
+//                   (contiguous along z, so its y pass runs over full tiles
+//                   and its z pass reads whole rows)
 //
 // A 3D real-to-complex transform is three passes: rows along x (two real rows
 // packed as one complex row), then the y axis, then the z axis.  The inverse
@@ -37,11 +40,24 @@ struct Half {
   static constexpr int HP = (H + 15) / 16 * 16;
 };
 
+// Radix plan of the contiguous row passes.  At N = 256 three stages with
+// 32-thread teams (8 rows per LDS batch) need half the prefetch registers of
+// two radix-16 stages in the pipelined inverse pass (measured faster).
+template <int N>
+struct RowPlan {
+  using type = FftPlan<N>;
+};
+template <>
+struct RowPlan<256> {
+  using type = Radices<8, 8, 4>;
+};
+
 template <int N>
 struct RowShape {
-  static constexpr int WB = FftShape<N>::RMAX;  // sequences per LDS batch
-  static constexpr int TS = FftShape<N>::TS;
-  static constexpr int NT = N;                  // threads per block
+  using Plan = typename RowPlan<N>::type;
+  static constexpr int WB = FftShape<N, Plan>::RMAX;  // sequences per LDS batch
+  static constexpr int TS = FftShape<N, Plan>::TS;
+  static constexpr int NT = N;                        // threads per block
   static constexpr int H = Half<N>::H;
   static constexpr int HP = Half<N>::HP;
 };
@@ -88,10 +104,12 @@ __device__ __forceinline__ void unpack_pair(const cplx<T>* z, int k, cplx<T>& A,
 // ---------------------------------------------------------------------------
 // Forward rows: real [rows][N] -> half spectra [rows][N/2+1]
 // ---------------------------------------------------------------------------
+// With nyq != nullptr the kx = N/2 entry of row r = z N + y goes to
+// nyq[y N + z] instead (one N^3 field: npairs = N^2 / 2).
 template <typename T, int N>
 __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                              long npairs, const cplx<T>* __restrict__ tw,
-                                                              int tstride) {
+                                                              cplx<T>* __restrict__ nyq, long npairs,
+                                                              const cplx<T>* __restrict__ tw, int tstride) {
   using S = RowShape<N>;
   __shared__ cplx<T> lds[S::WB * N];
   __shared__ cplx<T> twl[N];
@@ -107,15 +125,21 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restric
       lds[q * N + t] = v;
     }
     __syncthreads();
-    fft_team<N, -1, T>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    fft_team<N, -1, T, typename S::Plan>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
     for (int idx = t; idx < S::WB * S::H; idx += S::NT) {
       const int q = idx / S::H, k = idx % S::H;
       const long p = p0 + q;
       if (p < npairs) {
         cplx<T> A, B;
         unpack_pair<N>(lds + q * N, k, A, B);
-        out[(2 * p) * S::HP + k] = A;
-        out[(2 * p + 1) * S::HP + k] = B;
+        if (nyq && k == N / 2) {
+          const long r = 2 * p, z = r / N, y = r % N;
+          nyq[y * N + z] = A;
+          nyq[(y + 1) * N + z] = B;
+        } else {
+          out[(2 * p) * S::HP + k] = A;
+          out[(2 * p + 1) * S::HP + k] = B;
+        }
       }
     }
     __syncthreads();
@@ -183,7 +207,7 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
     __syncthreads();
     const long r = g / groups, p0 = (g % groups) * S::WB;
     if (g + gridDim.x < nitems) load(g + gridDim.x);
-    fft_team<N, +1, T>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    fft_team<N, +1, T, typename S::Plan>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
     ST* dst = out + r * ostride;
 #pragma unroll
     for (int q = 0; q < S::WB; ++q) {
@@ -339,7 +363,8 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 
 // ---------------------------------------------------------------------------
 // Forward z pass fused with |X|^2 binning.  src [outer][N][N * HP] holds the
-// x- and y-transformed spectra (padded rows).  Tiles cover live columns only
+// x- and y-transformed spectra (padded rows, kx < N/2) and nyq [outer][N][N]
+// their Nyquist planes kx = N/2 as [ky][z].  Tiles cover live columns only
 // and keep 128-byte aligned loads: "main" tiles are 16 consecutive kx < KM of
 // one y (KM = the largest multiple of 16 <= N/2), "rest" tiles gather the
 // remaining columns (kx in [KM, N/2], the Nyquist plane for N >= 32) of 16
@@ -375,7 +400,8 @@ struct BinTiles {
 };
 
 template <typename T, int N>
-__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src, long parts,
+__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src,
+                                                                const cplx<T>* __restrict__ nyq, long parts,
                                                                 const int8_t* __restrict__ bintab,
                                                                 int nbins, int b0, int nbc,
                                                                 double* __restrict__ part,
@@ -400,25 +426,21 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
   const cplx<T>* sp = src + spec * N * PLANE;
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
   for (int b = 0; b < nbc; ++b) slot[b * A::NT + t] = T(0);  // own column only
-  // Bins of |n|^2 <= (N/2)^2 (larger |n| are never binned), staged in LDS up to
-  // N = 256 (16 KB); visible after the first barrier of the tile loop.
-  constexpr int NB2 = (N / 2) * (N / 2) + 1;
-  constexpr bool kLdsBins = N <= 256;
-  __shared__ int btab_w[kLdsBins ? (NB2 + 3) / 4 : 1];
-  const int8_t* btab = reinterpret_cast<const int8_t*>(btab_w);
-  if constexpr (kLdsBins) {
-    const int* src_w = reinterpret_cast<const int*>(bintab);  // the table holds 3 (N/2)^2 + 1 bytes
-    for (int i = t; i < (NB2 + 3) / 4; i += A::NT) btab_w[i] = src_w[i];
-  }
+  constexpr int NB2 = (N / 2) * (N / 2) + 1;  // |n|^2 > (N/2)^2 is never binned
   cplx<T> pre[L];
+  const cplx<T>* nq = nyq + spec * N * N;
   const auto load = [&](long tile) {
     int ky, kx;
     BT::column(tile, cc, ky, kx);
     const bool live = ky >= 0;
-    const long off = static_cast<long>(j) * PLANE + static_cast<long>(live ? ky : 0) * HP + kx;  // valid either way
+    const long kyv = live ? ky : 0;  // a valid address either way
+    // the Nyquist column kx = N/2 sits in its own plane [ky][z]
+    const bool nqc = kx == N / 2;
+    const cplx<T>* base = nqc ? nq + kyv * N + j : sp + static_cast<long>(j) * PLANE + kyv * HP + kx;
+    const long step = nqc ? static_cast<long>(NSTEP) : static_cast<long>(NSTEP) * PLANE;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-      const cplx<T> v = sp[off + static_cast<long>(k) * NSTEP * PLANE];
+      const cplx<T> v = base[k * step];
       pre[k] = live ? v : cplx<T>{T(0), T(0)};
     }
   };
@@ -446,7 +468,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
       const cplx<T> x = lds[kz * A::TI + cc];
       const int n2 = nz * nz + cyx;
       int bin = -1;
-      if (ky >= 0 && n2 < NB2) bin = (kLdsBins ? btab[n2] : bintab[n2]) - b0;
+      if (ky >= 0 && n2 < NB2) bin = bintab[n2] - b0;
       const int bb = (bin >= 0 && bin < nbc) ? bin : -1;
       if (bb != cur) {
         if (cur >= 0) slot[cur * A::NT + t] += run;
@@ -552,13 +574,13 @@ struct IonShape {
 // owns cell (row 2p + t / N, x = t % N).  The smoothed values of its cell stay
 // in registers while every walker of the group is processed, so the resident
 // smoothed boxes are read once per group.  Two real rows are transformed as
-// one complex row.  Output: spec[w][row][kx] for w < nw (streaming stores),
-// and per-block x_HI sums xpart[w][block].
+// one complex row.  Output: spec[w][row][kx < N/2] (streaming stores), the
+// Nyquist plane nyq[w][y][z], and per-block x_HI sums xpart[w][block].
 template <typename T, typename S, int N>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ delta, int nr, const WalkerConst<T>* __restrict__ wc,
-    const T* __restrict__ thr, int nw, T tb, T dc, cplx<T>* __restrict__ spec, double* __restrict__ xpart,
-    const cplx<T>* __restrict__ tw, int tstride) {
+    const T* __restrict__ thr, int nw, T tb, T dc, cplx<T>* __restrict__ spec, cplx<T>* __restrict__ nyq,
+    double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride) {
   using IS = IonShape<N>;
   constexpr size_t N3 = static_cast<size_t>(N) * N * N;
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
@@ -606,9 +628,16 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
         if (w < nw) {
           cplx<T> A, B;
           unpack_pair<N>(lds + q * N, k, A, B);
-          cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
-          store_stream(o + k, A);
-          store_stream(o + IS::HP + k, B);
+          if (k < N / 2) {
+            cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
+            store_stream(o + k, A);
+            store_stream(o + IS::HP + k, B);
+          } else {
+            const size_t z = static_cast<size_t>(2 * p) / N, y = static_cast<size_t>(2 * p) % N;
+            cplx<T>* o = nyq + (static_cast<size_t>(w) * N + y) * N + z;
+            o[0] = A;
+            o[N] = B;
+          }
         }
       }
       __syncthreads();
@@ -759,8 +788,7 @@ long bins_parts(int n, long outer) {
 template <typename T, int N>
 constexpr int bins_per_launch() {
   using A = AxisShape<N>;
-  constexpr long table = N <= 256 ? ((N / 2) * (N / 2) + 4) / 4 * 4 : 4;  // staged bin table
-  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>)) + table;
+  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
   constexpr long per = (XS21_BINS_LDS_BUDGET - stat) / (static_cast<long>(A::NT) * static_cast<long>(sizeof(T)));
   return per < 1 ? 1 : static_cast<int>(per);
 }
@@ -791,8 +819,9 @@ int half_pitch(int n) {
 }
 int max_bins() { return kMaxBins; }
 
-hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nrows, const void* tw, int ntab,
-                           hipStream_t s) {
+hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, void* nyq, long nrows, const void* tw,
+                           int ntab, hipStream_t s) {
+  if (nyq && nrows != static_cast<long>(n) * n) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
@@ -800,8 +829,8 @@ hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nro
       const long npairs = nrows / 2;
       const long groups = (npairs + RowShape<N>::WB - 1) / RowShape<N>::WB;
       hipLaunchKernelGGL((k_rows_r2c<T, N>), dim3(grid_for(groups, 8192)), dim3(RowShape<N>::NT), 0, s,
-                         static_cast<const T*>(in), static_cast<cplx<T>*>(out), npairs,
-                         static_cast<const cplx<T>*>(tw), ntab / N);
+                         static_cast<const T*>(in), static_cast<cplx<T>*>(out), static_cast<cplx<T>*>(nyq),
+                         npairs, static_cast<const cplx<T>*>(tw), ntab / N);
       return hipGetLastError();
     });
   });
@@ -878,8 +907,8 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
   });
 }
 
-hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const int8_t* bintab, int nbins,
-                            double* part, const void* tw, int ntab, hipStream_t s) {
+hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, const int8_t* bintab,
+                            int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
   if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535) return hipErrorInvalidValue;
   const long parts = bins_parts(n, outer);
   return with_real(dtype, [&](auto tv) {
@@ -892,7 +921,8 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const
       for (int b0 = 0; b0 < nbins && e == hipSuccess; b0 += per) {
         const int nbc = nbins - b0 < per ? nbins - b0 : per;
         hipLaunchKernelGGL((k_axis_bins<T, N>), dim3(static_cast<unsigned>(outer * parts)), dim3(A::NT),
-                           static_cast<size_t>(nbc) * A::NT * sizeof(T), s, static_cast<const cplx<T>*>(src), parts,
+                           static_cast<size_t>(nbc) * A::NT * sizeof(T), s, static_cast<const cplx<T>*>(src),
+                           static_cast<const cplx<T>*>(nyq), parts,
                            bintab, nbins, b0, nbc, part, static_cast<const cplx<T>*>(tw), ntab / N);
         e = hipGetLastError();
       }
@@ -902,8 +932,8 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const
 }
 
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,
-                      const void* thr, int nw, double tb, double dc, void* spec, double* xpart, const void* tw,
-                      int ntab, hipStream_t s) {
+                      const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
+                      const void* tw, int ntab, hipStream_t s) {
   if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
@@ -914,7 +944,8 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
         hipLaunchKernelGGL((k_ion_rows<T, ST, N>), dim3(ion_grid(N)), dim3(IonShape<N>::NT), 0, s,
                            static_cast<const ST*>(dR), static_cast<const T*>(delta), nr,
                            static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr), nw,
-                           static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec), xpart,
+                           static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec),
+                           static_cast<cplx<T>*>(nyq), xpart,
                            static_cast<const cplx<T>*>(tw), ntab / N);
         return hipGetLastError();
       });

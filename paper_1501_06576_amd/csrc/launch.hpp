@@ -24,8 +24,10 @@ int max_bins();                         // bins per spectrum
 int half_pitch(int n);                  // row pitch (complex values) of a half spectrum
 
 // Real rows [nrows][n] of `dtype` -> half-spectrum rows [nrows][half_pitch(n)].
-hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, long nrows, const void* tw, int ntab,
-                           hipStream_t s);
+// With nyq != nullptr (one n^3 field, nrows = n^2) the kx = n/2 entries go to
+// the Nyquist plane nyq[y][z] instead of the rows.
+hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, void* nyq, long nrows, const void* tw,
+                           int ntab, hipStream_t s);
 // Half-spectrum rows -> real rows * scale, stored as `storage`, for `batch`
 // radii: radius b reads in + b * istride and writes out + b * ostride
 // (elements); entries with kx > cut[2 b + 1] (its kmax) are taken as zero
@@ -43,14 +45,16 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
                        long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
                        hipStream_t s);
-// Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] fused with
-// |X|^2 binning into part[outer][bins_tiles(n)][nbins] (FP64).
-hipError_t launch_axis_bins(int dtype, int n, const void* src, long outer, const int8_t* bintab, int nbins,
-                            double* part, const void* tw, int ntab, hipStream_t s);
-// Ionisation + dT_b + forward x pass for nw walkers on one box.
+// Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] (kx < n/2)
+// and their Nyquist planes nyq[outer][ky][z], fused with |X|^2 binning into
+// part[outer][bins_parts(n, outer)][nbins] (FP64).
+hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, const int8_t* bintab,
+                            int nbins, double* part, const void* tw, int ntab, hipStream_t s);
+// Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
+// [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,
-                      const void* thr, int nw, double tb, double dc, void* spec, double* xpart, const void* tw,
-                      int ntab, hipStream_t s);
+                      const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
+                      const void* tw, int ntab, hipStream_t s);
 // x_HI and dT_b boxes of one walker (either output may be null).
 hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* delta, int nr,
                               const void* wc, const void* thr, double tb, double dc, void* xhi, void* dtb,
