@@ -34,14 +34,17 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+# Sources of the path's kernels (the likelihood epilogue lives apart).
+KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "wave.hpp", "common.hpp", "launch.hpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the device sources; traffic figures are only reused for the same code."""
+    """Hash of the path's kernel sources; traffic figures are only reused for the same code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1501_06576_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + fh.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
 
 

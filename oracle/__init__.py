@@ -1,3 +1,4 @@
-"""FP64 CPU oracle (test infrastructure only; see excursion_set.py)."""
+"""FP64 CPU oracle (test infrastructure only; see excursion_set.py and likelihood.py)."""
 from .excursion_set import *  # noqa: F401,F403
 from .excursion_set import Physics, Evaluation  # noqa: F401
+from . import likelihood  # noqa: F401
