@@ -3,7 +3,10 @@
 One step = the whole path over one batch: for each of the three boxes
 (256^3, 250 Mpc, z = 8, 9, 10) the forward FFT and every sharp-k smoothed box
 of the shared radius ladder, then for all 64 walkers the ionisation field,
-dT_b and binned P(k) on all three boxes.  value = walkers / step time.
+dT_b and binned P(k) on all three boxes, and each walker's chi^2 against a
+synthetic mock (the fiducial walker's Delta^2 on the same boxes, no noise,
+25 per cent modelling error, 0.15 <= k <= 1 Mpc^-1).  value = walkers / step
+time.
 
 Also reported: the steady-state rate with the smoothed boxes resident (the MCMC
 loop), the plain per-walker form (recomputes the forward FFT and all smoothed
@@ -31,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # Vector ALU issue peak without packed FP32 (disabled in this build): 256 CUs x
 # 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FIDUCIAL = (30.0, 15.0, 5e4)  # zeta, R_mfp [Mpc], T_vir [K] of the mock
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -102,14 +106,24 @@ def main():
     nbmax = max(s.n_bins for s in wl.boxes)
     pk = torch.empty((nw, len(hs), nbmax), dtype=torch.float64, device="cuda")
     xhi = torch.empty((nw, len(hs)), dtype=torch.float64, device="cuda")
+    chi2 = torch.empty(nw, dtype=torch.float64, device="cuda")
+
+    # synthetic mock: the fiducial walker's Delta^2 on the same boxes
+    fid_pk, _ = ctx.eval_batch(hs, [FIDUCIAL])
+    fid_pk = fid_pk.cpu().numpy()
+    for i, h in enumerate(hs):
+        km, _counts = ctx.bins(h)
+        ctx.set_mock(h, km ** 3 * fid_pk[0, i, : len(km)] / (2 * np.pi ** 2))
 
     def step():
         for h in hs:
             ctx.resmooth(h)
         ctx.eval_batch(hs, walkers, pk, xhi)
+        ctx.chi2(hs, pk, chi2)
 
     def steady():
         ctx.eval_batch(hs, walkers, pk, xhi)
+        ctx.chi2(hs, pk, chi2)
 
     for _ in range(args.warmup):
         step()
@@ -195,6 +209,8 @@ def main():
         "plain_per_walker": None if ms_plain is None else
         {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
         "kernels": kernels,
+        "likelihood": {"chi2_min": round(float(chi2.min()), 4), "chi2_median": round(float(chi2.median()), 4),
+                       "mock": "fiducial walker (30, 15, 5e4) on the same boxes"},
         "roofline": ({"kernel": dom, "bound": "alu", "achieved": round(achieved_ops, 3),
                       "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4),
                       "algorithmic_ops_per_launch": ops_launch, "hbm": {"achieved": round(achieved, 1),

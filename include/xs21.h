@@ -206,6 +206,25 @@ xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out);
  * doubles.  Synchronous. */
 xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk);
 
+/* Likelihood epilogue (Section 2.5; redshifts combined as in Section 4).
+ * Sets the mock observation of `box`: delta2_mock[b] is the mock
+ * Delta^2_21 (mK^2) on the box's own bins and noise_sigma[b] its
+ * observational noise (mK^2; NULL = none).  A bin is fitted when it has modes
+ * and its mean |k| (xs21_box_bins) lies in [k_lo, k_hi] Mpc^-1 (0.15 and 1.0
+ * in the paper); its variance is noise^2 + (model_err * mock)^2
+ * (model_err = 0.25 in the paper), and bins of zero variance are left out.
+ * Both arrays are HOST, n_bins doubles, finite; model_err >= 0,
+ * 0 <= k_lo <= k_hi.  Synchronous (the table is uploaded before returning). */
+xs21_status xs21_set_mock(xs21_ctx* ctx, xs21_box box, const double* delta2_mock, const double* noise_sigma,
+                          double model_err, double k_lo, double k_hi);
+
+/* chi2[w] = sum over boxes[0..nb) and their fitted bins b of
+ * (Delta^2_w,b - mock_b)^2 / variance_b, with Delta^2_w,b = k_b^3 P_w,b / (2 pi^2)
+ * read from pk laid out as xs21_eval_batch writes it for the same box list
+ * ([nw][nb][max n_bins], DEVICE).  chi2: DEVICE, nw doubles.  Every listed box
+ * needs a mock (XS21_ESTATE otherwise).  Deterministic FP64; asynchronous. */
+xs21_status xs21_chi2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const double* pk, int nw, double* chi2);
+
 /* ---------------------------------------------------------------- kernel timing */
 
 /* Kernel classes timed by xs21_profile_read. */

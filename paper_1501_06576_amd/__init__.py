@@ -65,6 +65,8 @@ _SIGNATURES = {
     "xs21_smoothed": (_I, [_P, _I, _I, _P]),
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
     "xs21_resmooth": (_I, [_P, _I, _P]),
+    "xs21_set_mock": (_I, [_P, _I, _DP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "xs21_chi2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P]),
     "xs21_profile": (_I, [_P, _I]),
     "xs21_profile_read": (_I, [_P, _I, _DP, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
     "xs21_plan_ladder": (_I, [_D, _D, _D, _DP, _I, _IP]),
@@ -294,6 +296,30 @@ class Context:
         f = field.contiguous()
         _check(library().xs21_power_spectrum(self._ctx, box, ctypes.c_void_p(f.data_ptr()), _dptr(pk)))
         return pk
+
+    def set_mock(self, box: int, delta2_mock, noise_sigma=None, model_err=0.25, k_lo=0.15, k_hi=1.0):
+        """Mock Delta^2 (and optional noise) of `box` for the chi^2 epilogue; host arrays of n_bins."""
+        nb = self.boxes[box]["n_bins"]
+        m = np.ascontiguousarray(delta2_mock, dtype=np.float64)
+        if m.shape != (nb,):
+            raise ValueError(f"mock needs {nb} bins")
+        ns = None
+        if noise_sigma is not None:
+            ns = np.ascontiguousarray(noise_sigma, dtype=np.float64)
+            if ns.shape != (nb,):
+                raise ValueError(f"noise needs {nb} bins")
+        _check(library().xs21_set_mock(self._ctx, box, _dptr(m), None if ns is None else _dptr(ns),
+                                       float(model_err), float(k_lo), float(k_hi)))
+
+    def chi2(self, boxes: Sequence[int], pk, out=None):
+        """chi^2 per walker (device float64 [nw]) from the pk tensor eval_batch wrote for `boxes`."""
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        nw = pk.shape[0]
+        if out is None:
+            out = self.torch.empty(nw, dtype=self.torch.float64, device=self.device)
+        _check(library().xs21_chi2(self._ctx, bx, len(boxes), ctypes.c_void_p(pk.data_ptr()), nw,
+                                   ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def resmooth(self, box: int, new_delta=None):
         """Recomputes the forward FFT and the smoothed boxes of `box` (optionally from new device data)."""

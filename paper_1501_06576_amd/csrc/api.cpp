@@ -58,8 +58,9 @@ struct BoxRec {
   int storage = 0;
   int rbatch = 1;             // radii smoothed per launch
   std::vector<long> cut;      // (n2max, kmax) per ladder radius
+  bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
-  size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_dR = 0;
+  size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_dR = 0, off_like = 0;
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
   size_t half() const { return static_cast<size_t>(n / 2 + 1); }
@@ -235,6 +236,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     off += align_up(b.nbins * 8);
     b.off_cut = off;
     off += align_up(b.cut.size() * sizeof(long));
+    b.off_like = off;
+    off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
     b.off_delta = off;
     off += align_up(b.cells() * real_size(b.dtype));
     b.off_dR = off;
@@ -873,6 +876,57 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
                                       0, ctx->stream));
   HIPCHECK(ctx, hipMemcpyAsync(pk, outs, b.nbins * 8, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_set_mock(xs21_ctx* ctx, xs21_box box, const double* delta2_mock, const double* noise_sigma,
+                          double model_err, double k_lo, double k_hi) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!delta2_mock) return fail(XS21_EINVAL, "null mock");
+  if (!(std::isfinite(model_err) && model_err >= 0)) return fail(XS21_EINVAL, "model_err must be finite and >= 0");
+  if (!(std::isfinite(k_lo) && std::isfinite(k_hi) && k_lo >= 0 && k_lo <= k_hi))
+    return fail(XS21_EINVAL, "need 0 <= k_lo <= k_hi, finite");
+  BoxRec& b = ctx->boxes[box];
+  const int nb = b.nbins;
+  std::vector<double> tab(3 * static_cast<size_t>(nb));
+  for (int i = 0; i < nb; ++i) {
+    const double m = delta2_mock[i], sg = noise_sigma ? noise_sigma[i] : 0.0;
+    if (!std::isfinite(m) || !std::isfinite(sg)) return fail(XS21_EINVAL, "non-finite mock or noise in bin %d", i);
+    const double k = b.kmean[i];
+    const bool fitted = b.counts[i] > 0 && k >= k_lo && k <= k_hi;
+    constexpr double kPi = 3.14159265358979323846;
+    tab[i] = k * k * k / (2.0 * kPi * kPi);
+    tab[nb + i] = m;
+    tab[2 * nb + i] = fitted ? sg * sg + (model_err * m) * (model_err * m) : 0.0;
+  }
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_like, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  b.mock_set = true;
+  return XS21_OK;
+}
+
+xs21_status xs21_chi2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const double* pk, int nw, double* chi2) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (!boxes || nb < 1 || !pk || nw < 1 || !chi2) return fail(XS21_EINVAL, "empty or null argument");
+  int nbmax = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (xs21_status s = check_box(ctx, boxes[i])) return s;
+    if (!ctx->boxes[boxes[i]].mock_set) return fail(XS21_ESTATE, "box %d has no mock (xs21_set_mock)", boxes[i]);
+    nbmax = std::max(nbmax, ctx->boxes[boxes[i]].nbins);
+  }
+  for (int i = 0; i < nb; ++i) {
+    const BoxRec& b = ctx->boxes[boxes[i]];
+    HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, static_cast<double>(nw) * b.nbins * 16, [&] {
+      return xs21::launch_chi2(pk + static_cast<long>(i) * nbmax, static_cast<long>(nb) * nbmax, nw,
+                               reinterpret_cast<const double*>(ctx->ws + b.off_like), b.nbins, chi2, i == 0,
+                               ctx->stream);
+    }));
+  }
   return XS21_OK;
 }
 

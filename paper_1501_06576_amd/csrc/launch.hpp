@@ -63,6 +63,11 @@ hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, con
 hipError_t launch_finalize(int nwalkers, const double* part, long ntiles, int nbins, const double* xpart, long nblk,
                            const double* counts, double pscale, double inv_cells, double* pk, long pk_stride,
                            int nbins_out, double* xhi, long xhi_stride, hipStream_t s);
+// chi^2 of one box for nw walkers from their P(k) rows pk + w * pk_stride:
+// tab = [k_b^3 / (2 pi^2)][mock Delta^2][variance, 0 = bin not fitted], each
+// nbins long; adds to chi2[w], or sets it when first != 0.
+hipError_t launch_chi2(const double* pk, long pk_stride, int nw, const double* tab, int nbins, double* chi2,
+                       int first, hipStream_t s);
 // out[i] = (dtype) in[i] for `count` stored values.
 hipError_t launch_cast(int dtype, int storage, const void* in, void* out, size_t count, hipStream_t s);
 

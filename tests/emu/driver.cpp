@@ -62,6 +62,7 @@ int main(int argc, char** argv) {
   std::vector<int> box_dtype, box_n;
   std::vector<std::vector<char>> box_data;
   std::list<std::vector<char>> staged;  // inputs of queued device work, kept to the end
+  std::vector<double> last_pk;           // P(k) of the last batch (device memory is host memory here)
   std::string out = ".";
   xs21_ctx* ctx = nullptr;
   void* ws = nullptr;
@@ -126,6 +127,30 @@ int main(int argc, char** argv) {
       CHECK(xs21_sync(ctx));
       write_file(out + "/batch" + tag + "_pk.bin", pk.data(), pk.size() * 8);
       write_file(out + "/batch" + tag + "_xhi.bin", xm.data(), xm.size() * 8);
+      last_pk = pk;
+    } else if (cmd == "mock") {
+      // mock <box> <mock file> <noise file|-> <model_err> <k_lo> <k_hi>
+      int b;
+      std::string mf, nf;
+      double me, klo, khi;
+      is >> b >> mf >> nf >> me >> klo >> khi;
+      auto m = read_file(mf);
+      std::vector<char> nz;
+      if (nf != "-") nz = read_file(nf);
+      CHECK(xs21_set_mock(ctx, b, reinterpret_cast<const double*>(m.data()),
+                          nz.empty() ? nullptr : reinterpret_cast<const double*>(nz.data()), me, klo, khi));
+    } else if (cmd == "chi2") {
+      // chi2 [tag]: chi^2 of every walker over all boxes from the last batch's P(k)
+      std::string tag;
+      is >> tag;
+      const int nb = static_cast<int>(box_n.size());
+      std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
+      const int nw = static_cast<int>(walkers.size());
+      std::vector<double> c2(nw, -1.0);
+      CHECK(xs21_chi2(ctx, bx.data(), nb, last_pk.data(), nw, c2.data()));
+      CHECK(xs21_sync(ctx));
+      write_file(out + "/chi2" + tag + ".bin", c2.data(), c2.size() * 8);
     } else if (cmd == "resmooth") {
       // resmooth <box> <file|->: new density (same dtype and size) or the current one
       int b;

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 EMU = os.path.join(HERE, "emu")
 BIN = os.path.join(EMU, "_build", "xs21_emu")
-SRC = [os.path.join(ROOT, "paper_1501_06576_amd", "csrc", f) for f in ("kernels.hip", "api.cpp", "plan.cpp")]
+SRC = [os.path.join(ROOT, "paper_1501_06576_amd", "csrc", f)
+       for f in ("kernels.hip", "likelihood.hip", "api.cpp", "plan.cpp")]
 EXTRA = [os.path.join(EMU, "emu_runtime.cpp"), os.path.join(EMU, "driver.cpp")]
 
 
@@ -40,7 +41,7 @@ def build() -> str:
     # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 2 bins per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
            "-DXS21_PIPE_BLOCKS=3", "-DXS21_BINS_LDS_BUDGET=17664",
-           "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], "-x", "none", *SRC[1:], *EXTRA,
+           "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], SRC[1], "-x", "none", *SRC[2:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

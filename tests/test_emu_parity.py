@@ -171,3 +171,50 @@ def test_emu_resmooth_between_batches():
     shared = oracle.shared_radii(16, 12.0, PHYS)
     got = run.read("sm_b1_j2.bin", np.float64, (16, 16, 16))
     np.testing.assert_allclose(got, oracle.smooth(np.fft.rfftn(new1), 16, 12.0, shared[2]), atol=1e-13)
+
+
+def test_emu_chi2_epilogue():
+    # chi^2 against a mock (the fiducial walker's oracle Delta^2) over the
+    # fitted bins of two boxes, one with noise and one without
+    specs = [(16, 64.0, 9.0, 4), (8, 40.0, 8.0, 3)]
+    walkers = EDGE[:3]
+    run = eh.EmuRun(storage="f64", max_walkers=2, phys={"pk_amp": AMP})
+    boxes, mocks, noises = [], [], []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=80 + i, amp=AMP, dtype=np.float64)
+        boxes.append(d)
+        run.box(d, box, z, nb)
+        fid = oracle.evaluate(d, box, z, (30.0, 15.0, 5e4), oracle.walker_radii(oracle.shared_radii(n, box, PHYS), 15.0),
+                              nb, PHYS)
+        mocks.append(fid.delta2)
+        noises.append(np.linspace(0.5, 2.0, nb) if i == 0 else None)
+    for w in walkers:
+        run.walker(*w)
+    run.cmd("prepare")
+    run.cmd(f"batch {max(s[3] for s in specs)} A")
+    for i in range(len(specs)):
+        mp = run.write_array(f"mock{i}.bin", mocks[i])
+        npth = run.write_array(f"noise{i}.bin", noises[i]) if noises[i] is not None else "-"
+        run.cmd(f"mock {i} {mp} {npth} 0.25 0.15 1.0")
+    run.cmd("chi2 A")
+    run.run()
+    nbmax = max(s[3] for s in specs)
+    pk = run.read("batchA_pk.bin", np.float64, (len(walkers), len(specs), nbmax))
+    got = run.read("chi2A.bin", np.float64)
+    for wi, w in enumerate(walkers):
+        own, ref, scale = [], [], 0.0
+        for bi, (n, box, z, nb) in enumerate(specs):
+            shared = oracle.shared_radii(n, box, PHYS)
+            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+            noise = noises[bi] if noises[bi] is not None else np.zeros(nb)
+            d2_own = ev.k_mean ** 3 * pk[wi, bi, :nb] / (2 * np.pi ** 2)
+            own.append(oracle.likelihood.chi2(d2_own, mocks[bi], noise, ev.k_mean, ev.counts))
+            ref.append(oracle.likelihood.chi2(ev.delta2, mocks[bi], noise, ev.k_mean, ev.counts))
+            # size of the statistic for a model of zero power: sets the absolute tolerance
+            scale += oracle.likelihood.chi2(np.zeros(nb), mocks[bi], noise, ev.k_mean, ev.counts)
+        assert scale > 0
+        # the epilogue itself: the oracle's statistic on the library's own P(k)
+        # (walker 0 is the fiducial walker itself: chi^2 ~ 0)
+        assert got[wi] == pytest.approx(oracle.likelihood.chi2_total(own), rel=1e-12, abs=1e-14 * scale)
+        # end to end against the oracle's P(k) (FP64 path)
+        assert got[wi] == pytest.approx(oracle.likelihood.chi2_total(ref), rel=1e-9, abs=1e-11 * scale)

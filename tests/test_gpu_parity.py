@@ -335,3 +335,48 @@ def test_large_512_box(xs):
     np.testing.assert_allclose(out["pk"], pk[5, 0], rtol=1e-6)
     assert out["xhi_mean"] == pytest.approx(xhi[5, 0], abs=1e-6)
     ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_chi2_epilogue(xs, dtype):
+    """chi^2 over two redshifts against a mock (the fiducial walker's oracle
+    Delta^2), noise on one box: the epilogue on the library's own P(k) to FP64
+    round-off, and end to end within the bound that the P(k) tolerance implies."""
+    n, box, nb = 64, 128.0, 12
+    npd = np.float64 if dtype == "f64" else np.float32
+    ptol = 1e-9 if dtype == "f64" else 1e-3
+    zs = (8.5, 9.5)
+    ctx = _ctx(xs)
+    boxes, hs, mocks, noises = [], [], [], []
+    for i, z in enumerate(zs):
+        d = synth.make_box(n, box, z, seed=47, amp=AMP, dtype=npd)
+        boxes.append(d)
+        hs.append(ctx.add_box(d, box, z, nb))
+    ctx.prepare(dtype, max_walkers=4, max_plain_radii=30)
+    shared = ctx.radii(hs[0])
+    for i, z in enumerate(zs):
+        fid = oracle.evaluate(boxes[i], box, z, (30.0, 15.0, 5e4), oracle.walker_radii(shared, 15.0), nb, PHYS)
+        mocks.append(fid.delta2)
+        noises.append(np.linspace(1.0, 3.0, nb) if i == 0 else np.zeros(nb))
+        ctx.set_mock(hs[i], fid.delta2, noises[i] if i == 0 else None)
+    pk_t, _ = ctx.eval_batch(hs, EDGE_WALKERS)
+    got = ctx.chi2(hs, pk_t).cpu().numpy()
+    pk = pk_t.cpu().numpy()
+    for wi, w in enumerate(EDGE_WALKERS):
+        own, ref, bound, scale = 0.0, 0.0, 0.0, 0.0
+        for i, z in enumerate(zs):
+            ev = oracle.evaluate(boxes[i], box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+            use = oracle.likelihood.likelihood_bins(ev.k_mean, ev.counts)
+            var = oracle.likelihood.bin_variance(mocks[i], noises[i])
+            d2_own = ev.k_mean ** 3 * pk[wi, i, :nb] / (2 * math.pi ** 2)
+            own += oracle.likelihood.chi2(d2_own, mocks[i], noises[i], ev.k_mean, ev.counts)
+            ref += oracle.likelihood.chi2(ev.delta2, mocks[i], noises[i], ev.k_mean, ev.counts)
+            scale += oracle.likelihood.chi2(np.zeros(nb), mocks[i], noises[i], ev.k_mean, ev.counts)
+            ok = use & (var > 0)
+            r = np.abs(ev.delta2 - mocks[i])[ok]
+            dd = ptol * np.abs(ev.delta2)[ok]
+            bound += float(np.sum((2 * r * dd + dd * dd) / var[ok]))
+        print(f"[chi2-{dtype} w{wi}] gpu={got[wi]:.6e} oracle={ref:.6e} bound={bound:.2e}", flush=True)
+        assert got[wi] == pytest.approx(own, rel=1e-12, abs=1e-14 * scale)
+        assert abs(got[wi] - ref) <= bound * 1.01 + 1e-12 * scale
+    ctx.close()
