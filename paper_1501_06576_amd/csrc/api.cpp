@@ -442,7 +442,7 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   });
   if (e != hipSuccess) return e;
   e = timed(c, st, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
-    return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, count,
+    return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, count, parts,
                                   reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, sl.part, tw, kNtab,
                                   st);
   });
@@ -866,7 +866,7 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
                                   ctx->stream));
   HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, sl.nyq, sl.nyq, 1, n, n, nullptr, 1, 0, 0, tw, kNtab,
                                   ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1,
+  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1, parts,
                                        reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.nbins, part, tw,
                                        kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;

@@ -450,26 +450,33 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
     for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
     __syncthreads();
     if (tile + parts < BT::COUNT) load(tile + parts);
-    fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
-    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1; |nz| is
-    // monotone there, so equal bins come in runs, each added to the thread's
-    // own slot column once
+    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1.  Their
+    // bins are loaded before the FFT, unconditionally (entry 0, the dropped DC
+    // mode, stands in for modes that are not binned), so that the loads
+    // overlap the transform.
     int ky, kx;
     BT::column(tile, cc, ky, kx);
     const int ny = ky < N / 2 ? ky : ky - N;
     const int cyx = ny * ny + kx * kx;
+    int bin[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int kz = j * M + m;
+      const int nz = kz < N / 2 ? kz : kz - N;
+      const int n2 = nz * nz + cyx;
+      bin[m] = bintab[(ky >= 0 && n2 < NB2) ? n2 : 0];
+    }
+    fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
+    // |nz| is monotone along m, so equal bins come in runs, each added to the
+    // thread's own slot column once
     const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
     int cur = -1;
     T run = T(0);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const int kz = j * M + m;
-      const int nz = kz < N / 2 ? kz : kz - N;
-      const cplx<T> x = lds[kz * A::TI + cc];
-      const int n2 = nz * nz + cyx;
-      int bin = -1;
-      if (ky >= 0 && n2 < NB2) bin = bintab[n2] - b0;
-      const int bb = (bin >= 0 && bin < nbc) ? bin : -1;
+      const cplx<T> x = lds[(j * M + m) * A::TI + cc];
+      const int b = bin[m] - b0;  // negative for modes that are not binned
+      const int bb = (b >= 0 && b < nbc) ? b : -1;
       if (bb != cur) {
         if (cur >= 0) slot[cur * A::NT + t] += run;
         run = T(0);
@@ -907,10 +914,10 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
   });
 }
 
-hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, const int8_t* bintab,
-                            int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
-  if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535) return hipErrorInvalidValue;
-  const long parts = bins_parts(n, outer);
+hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, long parts,
+                            const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
+  if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535 || parts < 1 || parts > bins_tiles(n))
+    return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {

@@ -47,9 +47,10 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
                        hipStream_t s);
 // Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] (kx < n/2)
 // and their Nyquist planes nyq[outer][ky][z], fused with |X|^2 binning into
-// part[outer][bins_parts(n, outer)][nbins] (FP64).
-hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, const int8_t* bintab,
-                            int nbins, double* part, const void* tw, int ntab, hipStream_t s);
+// part[outer][parts][nbins] (FP64); parts in [1, bins_tiles(n)], normally
+// bins_parts(n, outer).
+hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, long parts,
+                            const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s);
 // Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
 // [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,

@@ -38,7 +38,7 @@ def build() -> str:
         return BIN
     os.makedirs(os.path.dirname(BIN), exist_ok=True)
     # XS21_PIPE_BLOCKS=3: grid-stride kernels run 3 blocks, each over many
-    # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 2 bins per launch
+    # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 1 bin per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
            "-DXS21_PIPE_BLOCKS=3", "-DXS21_BINS_LDS_BUDGET=17664",
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], SRC[1], "-x", "none", *SRC[2:], *EXTRA,
