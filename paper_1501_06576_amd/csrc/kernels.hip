@@ -291,19 +291,29 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     if (!any) return;
   }
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
-  for (int l = t; l < N * A::TI; l += A::NT) {
-    const int n = l / A::TI, c = l % A::TI;
-    const long i = i0 + c;
-    cplx<T> v = {T(0), T(0)};
-    if (i < ilim) {
-      const long nn = n < N / 2 ? n : n - N;
-      bool live = true;
-      if constexpr (MODE == 1) live = column_n2<N>(i) + nn * nn <= n2max;
-      if constexpr (MODE == 2) live = nn * nn + i * i <= n2max;
-      if (live) v = src[base + n * inner + i];
-    }
-    lds[l] = v;
+  // every element is loaded (dead ones from the slice's first element, a valid
+  // address holding a finite value) before any is used, so the loads issue
+  // back to back
+  constexpr int L = N * A::TI / A::NT;
+  static_assert(A::NT % A::TI == 0, "a thread keeps one column");
+  const int c = t % A::TI;
+  const long i = i0 + c;
+  cplx<T> v[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int n = t / A::TI + k * (A::NT / A::TI);
+    const long nn = n < N / 2 ? n : n - N;
+    bool live = i < ilim;
+    if constexpr (MODE == 1) live = live && column_n2<N>(i) + nn * nn <= n2max;
+    if constexpr (MODE == 2) live = live && nn * nn + i * i <= n2max;
+    // a product, not a select, keeps the compiler from moving the load under
+    // a branch (the dead lanes' element is a finite value)
+    const cplx<T> x = src[live ? base + n * inner + i : base];
+    const T keep = live ? T(1) : T(0);
+    v[k] = {x.x * keep, x.y * keep};
   }
+#pragma unroll
+  for (int k = 0; k < L; ++k) lds[t + k * A::NT] = v[k];
   __syncthreads();
   fft_team<N, DIR, T, typename A::Plan>(lds + (t % A::TI), A::TI, t / A::TI, twl, 1);
   for (int l = t; l < N * A::TI; l += A::NT) {
