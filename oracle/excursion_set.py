@@ -69,6 +69,9 @@ class Physics:
         the upper bound of the paper's R_mfp prior).
     mmin_form: 0 = M_min = 1e8 (T/1e4)^1.5 ((1+z)/10)^-1.5 Msun; 1 = eq. (3).
     mu: mean molecular weight in eq. (3) (the paper does not fix it; 0.6).
+    velocity: include the line-of-sight velocity-gradient factor H / (dv_r/dr + H)
+        of eq. (4) in dT_b (off: the factor is 1).
+    dvdr_max: limit on |dv_r/dr| / H in that factor (the paper gives none; 0.2).
     """
     delta_c: float = 1.686
     omega_m: float = 0.27
@@ -82,6 +85,8 @@ class Physics:
     ladder_top: float = 20.0
     mmin_form: int = 0
     mu: float = 0.6
+    velocity: bool = False
+    dvdr_max: float = 0.2
 
 
 RHO_CRIT_H2 = 2.775e11  # critical density today in Msun Mpc^-3 h^-2
@@ -254,11 +259,43 @@ def ionization_field(delta: np.ndarray, box: float, z: float, zeta: float, t_vir
     return flagged, x_hi
 
 
+def velocity_gradient(delta: np.ndarray, axis: int = 0) -> np.ndarray:
+    """Line-of-sight gradient of the linear peculiar velocity, in units of -H.
+
+    Linear continuity (Section 2.2 evaluates eq. 4 with the velocity field of
+    the same density box): in Fourier space the gradient of the velocity
+    component along the line of sight is -f H (k_r^2 / k^2) delta_hat, with the
+    growth rate f = d ln D / d ln a = 1 for D proportional to 1 / (1 + z).
+    Returns g(x) with dv_r/dr / H = -g; the k = 0 mode gives 0.  The line of
+    sight is array axis `axis` (the first axis throughout this work).
+    """
+    d64 = np.asarray(delta, dtype=np.float64)
+    n = d64.shape[0]
+    dhat = scipy.fft.rfftn(d64, workers=FFT_WORKERS)
+    idx = mode_indices(n)
+    kk = idx[0] * idx[0] + idx[1] * idx[1] + idx[2] * idx[2]
+    kr2 = idx[axis] * idx[axis]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        w = np.where(kk > 0, kr2 / np.where(kk > 0, kk, 1), 0.0)
+    return scipy.fft.irfftn(dhat * w, s=d64.shape, workers=FFT_WORKERS)
+
+
+def velocity_factor(delta: np.ndarray, phys: Physics) -> np.ndarray:
+    """H / (dv_r/dr + H) of eq. (4): 1 / (1 + t) with t = dv_r/dr / H = -g,
+    t limited to [-dvdr_max, dvdr_max] (the paper states no limit; without one
+    the factor diverges where the linear gradient reaches -H)."""
+    t = np.clip(-velocity_gradient(delta), -phys.dvdr_max, phys.dvdr_max)
+    return 1.0 / (1.0 + t)
+
+
 def brightness_temperature(x_hi: np.ndarray, delta: np.ndarray, z: float,
                            phys: Physics) -> np.ndarray:
     """dT_b = tb0 x_HI (1 + delta) sqrt((1 + z) / 10) mK (eq. 4 with T_S >> T_gamma,
-    without the velocity-gradient and cosmology factors)."""
-    return phys.tb0_mK * x_hi * (1.0 + np.asarray(delta, dtype=np.float64)) * math.sqrt((1.0 + z) / 10.0)
+    without the cosmology factors), times H / (dv_r/dr + H) when phys.velocity."""
+    dtb = phys.tb0_mK * x_hi * (1.0 + np.asarray(delta, dtype=np.float64)) * math.sqrt((1.0 + z) / 10.0)
+    if phys.velocity:
+        dtb = dtb * velocity_factor(delta, phys)
+    return dtb
 
 
 # ---------------------------------------------------------------------------

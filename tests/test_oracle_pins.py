@@ -393,3 +393,44 @@ def test_whole_path_brute_force_n8():
                     cn[b] += 1
     np.testing.assert_allclose(ev.pk, ps / cn, rtol=1e-9)
     assert ev.xhi_mean == pytest.approx(x_hi.mean(), rel=1e-12)
+
+
+# ---------------------------------------------------------------- velocity-gradient factor (eq. 4)
+
+def _wave(n, m, amp):
+    g = np.indices((n, n, n))
+    return amp * np.cos(2 * np.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n)
+
+
+@pytest.mark.parametrize("m,share", [((2, 0, 0), 1.0), ((0, 3, 0), 0.0), ((0, 0, 1), 0.0),
+                                     ((1, 1, 0), 0.5), ((1, 1, 1), 1.0 / 3.0), ((-2, 1, 2), 4.0 / 9.0)])
+def test_velocity_gradient_of_plane_waves(m, share):
+    # a plane wave along k has gradient share (k_r / |k|)^2 of delta along the
+    # line of sight (the first axis), from linear continuity with f = 1
+    d = _wave(16, m, 0.3)
+    np.testing.assert_allclose(oracle.velocity_gradient(d), share * d, atol=1e-14)
+
+
+def test_velocity_gradients_of_three_sight_lines_sum_to_delta():
+    # k_x^2 + k_y^2 + k_z^2 = k^2: the three line-of-sight gradients add up to
+    # the density contrast minus its mean
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((16, 16, 16))
+    total = sum(oracle.velocity_gradient(d, axis=a) for a in range(3))
+    np.testing.assert_allclose(total, d - d.mean(), atol=1e-12)
+
+
+def test_velocity_factor_limits_and_off_switch():
+    d = _wave(16, (1, 0, 0), 1.0)        # gradient = delta, in [-1, 1]
+    phys = oracle.Physics(pk_amp=PHYS.pk_amp, velocity=True, dvdr_max=0.2)
+    f = oracle.velocity_factor(d, phys)
+    assert f.min() == pytest.approx(1 / 1.2) and f.max() == pytest.approx(1 / 0.8)
+    small = _wave(16, (1, 0, 0), 0.05)  # inside the limit: exactly 1 / (1 - delta)
+    np.testing.assert_allclose(oracle.velocity_factor(small, phys), 1 / (1 - small), rtol=1e-13)
+    x = np.full(d.shape, 0.7)
+    on = oracle.brightness_temperature(x, small, 9.0, phys)
+    off = oracle.brightness_temperature(x, small, 9.0, oracle.Physics(pk_amp=PHYS.pk_amp))
+    np.testing.assert_allclose(on, off / (1 - small), rtol=1e-13)
+    # a uniform box has no velocity gradient: the factor is 1
+    u = np.full((8, 8, 8), 0.4)
+    np.testing.assert_allclose(oracle.velocity_factor(u, phys), 1.0, atol=1e-15)
