@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-walkers", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-walker form")
+    ap.add_argument("--no-velocity", action="store_true",
+                    help="skip the variant with the velocity-gradient factor of eq. (4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -221,6 +223,36 @@ def main():
                      "traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 5),
                      "algorithmic_bytes_per_launch": bytes_launch, "source_hash": kernel_source_hash()},
     }
+
+    if not args.no_velocity:
+        # the same step with the velocity-gradient factor H / (dv_r/dr + H) in dT_b
+        log("timing the variant with the velocity-gradient factor")
+        vctx = xs.Context(0, phys=xs.physics(pk_amp=amp, velocity=1))
+        vhs = [vctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+        vctx.prepare(wl.storage, max_walkers=group, max_plain_radii=40)
+        vfid, _ = vctx.eval_batch(vhs, [FIDUCIAL])
+        vfid = vfid.cpu().numpy()
+        for i, h in enumerate(vhs):
+            km, _counts = vctx.bins(h)
+            vctx.set_mock(h, km ** 3 * vfid[0, i, : len(km)] / (2 * np.pi ** 2))
+
+        def vstep():
+            for h in vhs:
+                vctx.resmooth(h)
+            vctx.eval_batch(vhs, walkers, pk, xhi)
+            vctx.chi2(vhs, pk, chi2)
+
+        for _ in range(args.warmup):
+            vstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            vstep()
+        torch.cuda.synchronize()
+        ms_v = (time.perf_counter() - t0) * 1e3 / args.steps
+        result["velocity_term"] = {"ms_per_step": round(ms_v, 4), "walker_evals_per_s": round(nw / (ms_v * 1e-3), 2),
+                                   "note": "same step with dT_b times H / (dv_r/dr + H), |dv_r/dr| / H <= 0.2"}
+        vctx.close()
 
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on one walker x all boxes")

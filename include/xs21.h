@@ -81,7 +81,10 @@ typedef struct {
   double ladder_top;  /* top radius of the shared ladder, Mpc (20)                 */
   double mu;          /* mean molecular weight in eq. (3) (0.6)                    */
   int32_t mmin_form;  /* 0: M_min = 1e8 (T/1e4)^1.5 ((1+z)/10)^-1.5; 1: eq. (3)     */
-  int32_t reserved;
+  int32_t velocity;   /* 1: dT_b includes H / (dv_r/dr + H) of eq. (4), the linear
+                         line-of-sight velocity gradient of the box (first axis);
+                         0: that factor is 1 (default)                            */
+  double dvdr_max;    /* limit on |dv_r/dr| / H in that factor (0.2)               */
 } xs21_physics;
 
 /* One astrophysical parameter set (Section 2.1). */

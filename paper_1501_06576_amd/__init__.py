@@ -35,7 +35,7 @@ class Physics(ctypes.Structure):
                 ("h", ctypes.c_double), ("tb0_mK", ctypes.c_double), ("pk_amp", ctypes.c_double),
                 ("pk_k0", ctypes.c_double), ("z_ref", ctypes.c_double), ("radius_step", ctypes.c_double),
                 ("ladder_top", ctypes.c_double), ("mu", ctypes.c_double), ("mmin_form", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("velocity", ctypes.c_int32), ("dvdr_max", ctypes.c_double)]
 
 
 class Walker(ctypes.Structure):

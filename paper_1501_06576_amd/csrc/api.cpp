@@ -57,10 +57,10 @@ struct BoxRec {
   std::vector<double> counts, kmean;
   int storage = 0;
   int rbatch = 1;             // radii smoothed per launch
-  std::vector<long> cut;      // (n2max, kmax) per ladder radius
+  std::vector<long> cut;      // (n2max, kmax) per ladder radius, then one pair keeping every mode
   bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
-  size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_dR = 0, off_like = 0;
+  size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_od = 0, off_dR = 0, off_like = 0;
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
   size_t half() const { return static_cast<size_t>(n / 2 + 1); }
@@ -200,8 +200,11 @@ int radius_batch(const BoxRec& b) {
 int box_storage(const BoxRec& b, int storage) { return b.dtype == xs21::kF64 ? xs21::kF64 : storage; }
 
 // Scratch of each phase, per box; each region is the maximum over boxes.
-// Smoothing: the box spectrum + one spectrum per radius of a launch batch.
-size_t smooth_scratch(const BoxRec& b) { return (1 + static_cast<size_t>(b.rbatch)) * align_up(b.spec_bytes()); }
+// Smoothing: the box spectrum + one spectrum per radius of a launch batch
+// (at least two: the velocity-gradient field uses a spectrum and a real box).
+size_t smooth_scratch(const BoxRec& b) {
+  return (1 + static_cast<size_t>(std::max(b.rbatch, 2))) * align_up(b.spec_bytes());
+}
 
 // Evaluation: walker spectra, their Nyquist planes, bin partial sums, x_HI partial sums.
 size_t nyq_bytes(const BoxRec& b) { return static_cast<size_t>(b.n) * b.n * 2 * real_size(b.dtype); }
@@ -239,6 +242,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     b.off_like = off;
     off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
     b.off_delta = off;
+    off += align_up(b.cells() * real_size(b.dtype));
+    b.off_od = off;
     off += align_up(b.cells() * real_size(b.dtype));
     b.off_dR = off;
     off += align_up(static_cast<size_t>(b.nr()) * b.cells() * store_size(b.storage));
@@ -382,6 +387,43 @@ hipError_t smooth_box(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
   return hipSuccess;
 }
 
+// Density factor of dT_b for box b: odens = (1 + delta) times H / (dv_r/dr + H)
+// of eq. (4) when the context includes velocities, else 1 + delta.  The
+// gradient is the inverse FFT of (nz^2 / |n|^2) delta_hat (linear continuity
+// with growth rate 1, line of sight along the first axis); it reads the box
+// spectrum smooth_box left at the start of the scratch region.
+hipError_t density_factor(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
+  const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
+  const double rs = static_cast<double>(real_size(b.dtype));
+  const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
+  const void* delta = c->ws + b.off_delta;
+  void* od = c->ws + b.off_od;
+  if (!c->phys.velocity)
+    return timed(c, st, XS21_K_OTHER, 3 * cells * rs,
+                 [&] { return xs21::launch_los_factor(b.dtype, delta, nullptr, od, b.cells(), 0.0, st); });
+  unsigned char* hat = c->ws + c->lay.scratch;
+  unsigned char* spec = hat + align_up(b.spec_bytes());
+  unsigned char* g = spec + align_up(b.spec_bytes());
+  const void* tw = tw_ptr(c, b.dtype);
+  hipError_t e = timed(c, st, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 4, hat, spec, 1, n * hp, n * hp, nullptr, 1, 0, 0, tw, kNtab, st);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(c, st, XS21_K_AXIS_INV, 2 * modes * 2 * rs, [&] {
+    return xs21::launch_axis(b.dtype, b.n, +1, 0, spec, spec, n, hp, h, nullptr, 1, 0, 0, tw, kNtab, st);
+  });
+  if (e != hipSuccess) return e;
+  const long* full = reinterpret_cast<const long*>(c->ws + b.off_cut) + 2 * b.nr();
+  e = timed(c, st, XS21_K_ROWS_C2R, modes * 2 * rs + cells * rs, [&] {
+    return xs21::launch_rows_c2r(b.dtype, b.dtype, b.n, spec, g, n * n, 1.0 / cells, full, 1, 0,
+                                 static_cast<long>(b.cells()), tw, kNtab, st);
+  });
+  if (e != hipSuccess) return e;
+  return timed(c, st, XS21_K_OTHER, 4 * cells * rs, [&] {
+    return xs21::launch_los_factor(b.dtype, delta, g, od, b.cells(), c->phys.dvdr_max, st);
+  });
+}
+
 // Scratch of one evaluation of `count` walkers on one box: their x-transformed
 // spectra (kx < N/2), their Nyquist planes [y][z], then the binning pass's
 // FP64 partial sums, then the ionisation pass's x_HI partial sums.
@@ -415,7 +457,7 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   return timed(
       c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
       [&] {
-        return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_delta, nr, wc, thr, count, tb,
+        return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_od, nr, wc, thr, count, tb,
                                 c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
       },
       ion_ops);
@@ -478,6 +520,8 @@ xs21_status xs21_physics_default(xs21_physics* p) {
   p->ladder_top = 20.0;
   p->mu = 0.6;
   p->mmin_form = 0;
+  p->velocity = 0;
+  p->dvdr_max = 0.2;
   g_error.clear();
   return XS21_OK;
 }
@@ -554,8 +598,10 @@ xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_d
   if (b.nr() > xs21::max_radii())
     return fail(XS21_EUNSUPPORTED, "ladder of %d radii exceeds %d", b.nr(), xs21::max_radii());
   for (double r : b.radii) b.n2max.push_back(xs21::plan::n2max(r, box_mpc));
-  b.cut.resize(2 * b.radii.size());
+  b.cut.resize(2 * b.radii.size() + 2);
   for (size_t j = 0; j < b.radii.size(); ++j) cut_pair(b, b.radii[j], &b.cut[2 * j]);
+  b.cut[2 * b.radii.size()] = 3L * (n / 2) * (n / 2) + 1;  // every mode
+  b.cut[2 * b.radii.size() + 1] = n / 2;
   b.bintab = xs21::plan::bins(n, n_bins);
   xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
   if (on_device) {
@@ -659,6 +705,7 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
     else
       HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.host.data(), dbytes, hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, smooth_box(ctx, ctx->stream, b));
+    HIPCHECK(ctx, density_factor(ctx, ctx->stream, b));
   }
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& b : ctx->boxes) {
@@ -795,7 +842,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
     void* fd = hat + align_up(fbytes);
     const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
     HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_delta, nr, wc, thr, tbv,
+      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_od, nr, wc, thr, tbv,
                                       ctx->phys.delta_c, fx, fd, ctx->stream);
     }));
     if (x_hi) HIPCHECK(ctx, hipMemcpyAsync(x_hi, fx, fbytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -828,7 +875,7 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   ctx->upload_pending = true;
   const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
   HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_delta, b.nr(), wc,
+    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_od, b.nr(), wc,
                                     wc + align_up(b.wc_size()), tbv, ctx->phys.delta_c, x_hi, dtb, ctx->stream);
   }));
   return XS21_OK;
@@ -940,6 +987,7 @@ xs21_status xs21_resmooth(xs21_ctx* ctx, xs21_box box, const void* new_delta) {
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, new_delta, b.cells() * real_size(b.dtype),
                                  hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHECK(ctx, smooth_box(ctx, ctx->stream, b));
+  HIPCHECK(ctx, density_factor(ctx, ctx->stream, b));
   return XS21_OK;
 }
 

@@ -235,6 +235,9 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
 // MODE 3: one column (inner index ilim - 1) of each of TI consecutive outer
 //   slices per block (blockIdx.x picks the slices): the Nyquist column of a
 //   forward y pass, so that the main launch only covers full aligned tiles.
+// MODE 4: inverse z pass (inner index as in MODE 1) of the line-of-sight
+//   velocity gradient: each mode is weighted by nz^2 / |n|^2 on load (0 for
+//   the mean and the padding columns).
 // ---------------------------------------------------------------------------
 // |n|^2 without the z part of flat column i = y * HP + kx of a padded half
 // spectrum; padding columns (kx > N/2) get a value above every cutoff.
@@ -304,12 +307,19 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     const int n = t / A::TI + k * (A::NT / A::TI);
     const long nn = n < N / 2 ? n : n - N;
     bool live = i < ilim;
+    T wgt = T(1);
     if constexpr (MODE == 1) live = live && column_n2<N>(i) + nn * nn <= n2max;
     if constexpr (MODE == 2) live = live && nn * nn + i * i <= n2max;
+    if constexpr (MODE == 4) {
+      const int c2 = column_n2<N>(i);
+      const long k2 = c2 + nn * nn;
+      live = live && c2 < 0x3fffffff && k2 > 0;
+      wgt = live ? static_cast<T>(nn * nn) / static_cast<T>(k2) : T(0);
+    }
     // a product, not a select, keeps the compiler from moving the load under
     // a branch (the dead lanes' element is a finite value)
     const cplx<T> x = src[live ? base + n * inner + i : base];
-    const T keep = live ? T(1) : T(0);
+    const T keep = live ? wgt : T(0);
     v[k] = {x.x * keep, x.y * keep};
   }
 #pragma unroll
@@ -587,6 +597,8 @@ struct IonShape {
 };
 
 // Ionisation + brightness temperature + forward x pass for a group of walkers.
+// odens[cell] = (1 + delta) times the velocity-gradient factor of eq. (4)
+// (or 1), computed once per box by k_los_factor.
 // Each block owns row pairs (rows 2p, 2p+1 of the z-y plane stack); thread t
 // owns cell (row 2p + t / N, x = t % N).  The smoothed values of its cell stay
 // in registers while every walker of the group is processed, so the resident
@@ -595,7 +607,7 @@ struct IonShape {
 // Nyquist plane nyq[w][y][z], and per-block x_HI sums xpart[w][block].
 template <typename T, typename S, int N>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
-    const S* __restrict__ dR, const T* __restrict__ delta, int nr, const WalkerConst<T>* __restrict__ wc,
+    const S* __restrict__ dR, const T* __restrict__ odens, int nr, const WalkerConst<T>* __restrict__ wc,
     const T* __restrict__ thr, int nw, T tb, T dc, cplx<T>* __restrict__ spec, cplx<T>* __restrict__ nyq,
     double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride) {
   using IS = IonShape<N>;
@@ -617,7 +629,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
     const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
     T d[kNrMax];
     load_radii<T, S>(dR, N3, cell, nr, d);
-    const T od = T(1) + delta[cell];
+    const T od = odens[cell];
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
 #pragma unroll 1
@@ -663,9 +675,23 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   for (int w = t; w < nw; w += IS::NT) xpart[static_cast<size_t>(w) * gridDim.x + blockIdx.x] = acc[w];
 }
 
+// Per-cell density factor of dT_b (Section 2.2, eq. 4): odens = (1 + delta) /
+// (1 + t), t = dv_r/dr / H = -g limited to [-tmax, tmax], with g the
+// line-of-sight gradient field (g == nullptr: odens = 1 + delta).
+template <typename T>
+__global__ __launch_bounds__(256) void k_los_factor(const T* __restrict__ delta, const T* __restrict__ g,
+                                                    T* __restrict__ odens, size_t count, T tmax) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * 256) {
+    T f = T(1);
+    if (g) f = T(1) / (T(1) + min(max(-g[i], -tmax), tmax));
+    odens[i] = (T(1) + delta[i]) * f;
+  }
+}
+
 // Materialise x_HI and dT_b of one walker (same per-cell arithmetic as above).
 template <typename T, typename S, int N>
-__global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, const T* __restrict__ delta, int nr,
+__global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, const T* __restrict__ odens, int nr,
                                                      const WalkerConst<T>* __restrict__ wc,
                                                      const T* __restrict__ thr, T tb, T dc, T* __restrict__ xhi,
                                                      T* __restrict__ dtb) {
@@ -677,7 +703,7 @@ __global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, c
     load_radii<T, S>(dR, N3, cell, nr, d);
     const T x = cell_xhi<T, kNrMax>(d, c, thr, dc);
     if (xhi) xhi[cell] = x;
-    if (dtb) dtb[cell] = tb * x * (T(1) + delta[cell]);
+    if (dtb) dtb[cell] = tb * x * odens[cell];
   }
 }
 
@@ -877,8 +903,8 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
                        long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
                        hipStream_t s) {
-  if (ilim < 1 || ilim > inner || mode < 0 || mode > 2 || (mode != 0 && !cut) || batch < 1 || batch > 65535 ||
-      outer > 65535)
+  if (ilim < 1 || ilim > inner || mode < 0 || mode > 4 || mode == 3 || ((mode == 1 || mode == 2) && !cut) ||
+      batch < 1 || batch > 65535 || outer > 65535 || (mode == 4 && dir < 0))
     return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
@@ -915,6 +941,9 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
       } else if (mode == 2) {
         hipLaunchKernelGGL((k_axis<T, N, +1, 2>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
                            outer, tp, ts);
+      } else if (mode == 4) {
+        hipLaunchKernelGGL((k_axis<T, N, +1, 4>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
+                           outer, tp, ts);
       } else {
         hipLaunchKernelGGL((k_axis<T, N, +1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
                            outer, tp, ts);
@@ -948,7 +977,7 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, 
   });
 }
 
-hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,
+hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
                       const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
                       const void* tw, int ntab, hipStream_t s) {
   if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
@@ -959,7 +988,7 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
       return with_n(n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
         hipLaunchKernelGGL((k_ion_rows<T, ST, N>), dim3(ion_grid(N)), dim3(IonShape<N>::NT), 0, s,
-                           static_cast<const ST*>(dR), static_cast<const T*>(delta), nr,
+                           static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
                            static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr), nw,
                            static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec),
                            static_cast<cplx<T>*>(nyq), xpart,
@@ -970,7 +999,7 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
   });
 }
 
-hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* delta, int nr,
+hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
                               const void* wc, const void* thr, double tb, double dc, void* xhi, void* dtb,
                               hipStream_t s) {
   if (nr < 1 || nr > kNrMax) return hipErrorInvalidValue;
@@ -982,7 +1011,7 @@ hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, con
         constexpr int N = decltype(nc)::value;
         const long cells = static_cast<long>(N) * N * N;
         hipLaunchKernelGGL((k_materialize<T, ST, N>), dim3(grid_for((cells + 255) / 256, 16384)), dim3(256), 0, s,
-                           static_cast<const ST*>(dR), static_cast<const T*>(delta), nr,
+                           static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
                            static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr),
                            static_cast<T>(tb), static_cast<T>(dc), static_cast<T*>(xhi), static_cast<T*>(dtb));
         return hipGetLastError();
@@ -998,6 +1027,17 @@ hipError_t launch_finalize(int nwalkers, const double* part, long ntiles, int nb
   hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>(nwalkers)), dim3(256), 0, s, part, ntiles, nbins, xpart,
                      nblk, counts, pscale, inv_cells, pk, pk_stride, nbins_out, xhi, xhi_stride);
   return hipGetLastError();
+}
+
+hipError_t launch_los_factor(int dtype, const void* delta, const void* g, void* odens, size_t count, double tmax,
+                             hipStream_t s) {
+  return with_real(dtype, [&](auto tv) {
+    using T = decltype(tv);
+    hipLaunchKernelGGL((k_los_factor<T>), dim3(grid_for(static_cast<long>((count + 255) / 256), 16384)), dim3(256), 0,
+                       s, static_cast<const T*>(delta), static_cast<const T*>(g), static_cast<T*>(odens), count,
+                       static_cast<T>(tmax));
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_cast(int dtype, int storage, const void* in, void* out, size_t count, hipStream_t s) {

@@ -40,8 +40,10 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
 // sstride and writes dst + b * dstride (elements).  mode 0 plain; mode 1 the
 // z pass of a sharp-k smoothing with cutoff |n|^2 <= cut[2 b] (columns
 // outside the disk skipped); mode 2 the y pass of a smoothing (only entries
-// with ny^2 + kx^2 <= cut[2 b] read, columns kx <= cut[2 b + 1]).  cut is a
-// device array of (n2max, kmax) pairs, unused by mode 0.
+// with ny^2 + kx^2 <= cut[2 b] read, columns kx <= cut[2 b + 1]); mode 4 an
+// inverse z pass weighting each mode by nz^2 / |n|^2 (the line-of-sight
+// velocity gradient).  cut is a device array of (n2max, kmax) pairs, used by
+// modes 1 and 2 only.
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
                        long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
                        hipStream_t s);
@@ -53,11 +55,11 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, 
                             const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s);
 // Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
 // [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
-hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* delta, int nr, const void* wc,
+hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
                       const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
                       const void* tw, int ntab, hipStream_t s);
 // x_HI and dT_b boxes of one walker (either output may be null).
-hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* delta, int nr,
+hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
                               const void* wc, const void* thr, double tb, double dc, void* xhi, void* dtb,
                               hipStream_t s);
 // Deterministic reduction of the bin and x_HI partial sums, one walker per block.
@@ -69,6 +71,10 @@ hipError_t launch_finalize(int nwalkers, const double* part, long ntiles, int nb
 // nbins long; adds to chi2[w], or sets it when first != 0.
 hipError_t launch_chi2(const double* pk, long pk_stride, int nw, const double* tab, int nbins, double* chi2,
                        int first, hipStream_t s);
+// odens = (1 + delta) / (1 + clamp(-g, -tmax, tmax)) per cell (g == nullptr:
+// 1 + delta), the density factor of dT_b with the velocity-gradient term.
+hipError_t launch_los_factor(int dtype, const void* delta, const void* g, void* odens, size_t count, double tmax,
+                             hipStream_t s);
 // out[i] = (dtype) in[i] for `count` stored values.
 hipError_t launch_cast(int dtype, int storage, const void* in, void* out, size_t count, hipStream_t s);
 

@@ -42,7 +42,8 @@ bool valid_physics(const xs21_physics& p) {
   return std::isfinite(p.delta_c) && finite_pos(p.omega_m) && std::isfinite(p.omega_l) && finite_pos(p.h) &&
          std::isfinite(p.tb0_mK) && finite_pos(p.pk_amp) && finite_pos(p.pk_k0) && std::isfinite(p.z_ref) &&
          p.z_ref > -1.0 && std::isfinite(p.radius_step) && p.radius_step > 1.0 && finite_pos(p.ladder_top) &&
-         finite_pos(p.mu) && (p.mmin_form == 0 || p.mmin_form == 1);
+         finite_pos(p.mu) && (p.mmin_form == 0 || p.mmin_form == 1) && (p.velocity == 0 || p.velocity == 1) &&
+         std::isfinite(p.dvdr_max) && p.dvdr_max >= 0.0 && p.dvdr_max < 1.0;
 }
 
 bool valid_walker(const xs21_walker& w) { return finite_pos(w.zeta) && finite_pos(w.r_mfp) && finite_pos(w.t_vir); }

@@ -79,6 +79,8 @@ int main(int argc, char** argv) {
       else if (key == "ladder_top") phys.ladder_top = v;
       else if (key == "radius_step") phys.radius_step = v;
       else if (key == "mmin_form") phys.mmin_form = static_cast<int>(v);
+      else if (key == "velocity") phys.velocity = static_cast<int>(v);
+      else if (key == "dvdr_max") phys.dvdr_max = v;
     } else if (cmd == "storage") {
       std::string s;
       is >> s;

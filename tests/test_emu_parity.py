@@ -18,15 +18,15 @@ EDGE = [(30.0, 15.0, 5e4), (100.0, 20.0, 1e4), (5.0, 5.0, 1e6), (0.4, 12.0, 2e4)
         (0.8, 9.0, 2e4)]
 
 
-def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True, tag="", fields=True):
+def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True, tag="", fields=True, phys=PHYS):
     nbmax = max(s[3] for s in specs)
     pk = run.read(f"batch{tag}_pk.bin", np.float64, (len(walkers), len(specs), nbmax))
     xm = run.read(f"batch{tag}_xhi.bin", np.float64, (len(walkers), len(specs)))
     for bi, (n, box, z, nb) in enumerate(specs):
         dt = boxes[bi].dtype
-        shared = oracle.shared_radii(n, box, PHYS)
+        shared = oracle.shared_radii(n, box, phys)
         for wi, w in enumerate(walkers):
-            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.walker_radii(shared, w[1]), nb, phys)
             ok = ev.counts > 0
             scale = max(ev.pk[ok].max(), 1e-30)
             np.testing.assert_allclose(pk[wi, bi, :nb][ok], ev.pk[ok], rtol=tol_pk, atol=tol_pk * scale)
@@ -37,7 +37,7 @@ def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True, tag="", fi
                 assert np.mean((x == 0) != ev.flagged) <= flips_max
         if plain:
             w = walkers[0]
-            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.plain_radii(w[1], n, box, PHYS), nb, PHYS)
+            ev = oracle.evaluate(boxes[bi], box, z, w, oracle.plain_radii(w[1], n, box, phys), nb, phys)
             x = run.read(f"plain_b{bi}_w0_xhi.bin", dt, (n, n, n))
             d = run.read(f"plain_b{bi}_w0_dtb.bin", dt, (n, n, n))
             p = run.read(f"plain_b{bi}_w0_pk.bin", np.float64)[:nb]
@@ -49,8 +49,8 @@ def _check(run, boxes, specs, walkers, tol_pk, flips_max, plain=True, tag="", fi
             np.testing.assert_array_equal(run.read(f"plain_b{bi}_w0_cnt.bin", np.float64)[:nb], ev.counts)
 
 
-def _run(storage, specs, walkers, max_walkers, dtype, extra=()):
-    run = eh.EmuRun(storage=storage, max_walkers=max_walkers, phys={"pk_amp": AMP})
+def _run(storage, specs, walkers, max_walkers, dtype, extra=(), phys=None):
+    run = eh.EmuRun(storage=storage, max_walkers=max_walkers, phys=phys or {"pk_amp": AMP})
     boxes = []
     for i, (n, box, z, nb) in enumerate(specs):
         d = synth.make_box(n, box, z, seed=60 + i, amp=AMP, dtype=dtype)
@@ -218,3 +218,11 @@ def test_emu_chi2_epilogue():
         assert got[wi] == pytest.approx(oracle.likelihood.chi2_total(own), rel=1e-12, abs=1e-14 * scale)
         # end to end against the oracle's P(k) (FP64 path)
         assert got[wi] == pytest.approx(oracle.likelihood.chi2_total(ref), rel=1e-9, abs=1e-11 * scale)
+
+
+def test_emu_velocity_factor():
+    # dT_b with the line-of-sight velocity-gradient factor of eq. (4)
+    specs = [(16, 24.0, 9.0, 4)]
+    phys = oracle.Physics(pk_amp=AMP, velocity=True, dvdr_max=0.2)
+    run, boxes = _run("f64", specs, EDGE[:3], 2, np.float64, phys={"pk_amp": AMP, "velocity": 1, "dvdr_max": 0.2})
+    _check(run, boxes, specs, EDGE[:3], 1e-11, 0.0, phys=phys)

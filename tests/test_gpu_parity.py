@@ -380,3 +380,35 @@ def test_chi2_epilogue(xs, dtype):
         assert got[wi] == pytest.approx(own, rel=1e-12, abs=1e-14 * scale)
         assert abs(got[wi] - ref) <= bound * 1.01 + 1e-12 * scale
     ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_velocity_factor(xs, dtype):
+    """dT_b with the velocity-gradient factor H / (dv_r/dr + H) of eq. (4):
+    batched walkers and the plain form against the oracle with velocities."""
+    n, box, z, nb = 64, 128.0, 8.0, 12
+    npd = np.float64 if dtype == "f64" else np.float32
+    d = synth.make_box(n, box, z, seed=53, amp=AMP, dtype=npd)
+    phys = oracle.Physics(pk_amp=AMP, velocity=True, dvdr_max=0.2)
+    ctx = _ctx(xs, velocity=1, dvdr_max=0.2)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare(dtype, max_walkers=4, max_plain_radii=30)
+    walkers = EDGE_WALKERS[:5]
+    pk, xhi = ctx.eval_batch([b], walkers)
+    pk = pk.cpu().numpy()
+    shared = ctx.radii(b)
+    plain_off = oracle.evaluate(d, box, z, walkers[0], oracle.walker_radii(shared, walkers[0][1]), nb,
+                                oracle.Physics(pk_amp=AMP))
+    for i, w in enumerate(walkers):
+        ev = oracle.evaluate(d, box, z, w, oracle.walker_radii(shared, w[1]), nb, phys)
+        flips, rel = report(f"velocity-{dtype} w{i}", None, ev, pk[i, 0], float(xhi[i, 0]))
+        assert rel <= (1e-9 if dtype == "f64" else 1e-3)
+        if i == 0:
+            # the factor matters: P(k) moves well beyond the tolerance without it
+            assert np.abs(ev.pk / plain_off.pk - 1.0)[ev.counts > 0].max() > 1e-2
+    out = ctx.eval(b, walkers[0])
+    ev = oracle.evaluate(d, box, z, walkers[0], oracle.plain_radii(walkers[0][1], n, box, phys), nb, phys)
+    same = (out["x_hi"] == 0) == ev.flagged
+    tol = 1e-8 if dtype == "f64" else 2e-3
+    assert np.abs(out["dtb"] - ev.dtb)[same].max() <= tol * np.abs(ev.dtb).max()
+    ctx.close()
