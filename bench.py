@@ -12,7 +12,9 @@ Also reported: the steady-state rate with the smoothed boxes resident (the MCMC
 loop), the plain per-walker form (recomputes the forward FFT and all smoothed
 boxes of the walker's own radii per evaluation), Gcell-R/s, the roofline of the
 dominant kernel (HIP events on the library stream inside the timed steps,
-algorithmic bytes), and the FP64 CPU oracle timed on a bounded sample.
+algorithmic bytes), the FP64 CPU oracle timed on a bounded sample, and the
+same step with the velocity-gradient factor of eq. (4) and with two-population
+walkers (the efficiency of eq. (9)).
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FIDUCIAL = (30.0, 15.0, 5e4)  # zeta, R_mfp [Mpc], T_vir [K] of the mock
+# zeta0, R_mfp [Mpc], T_feed [K], alpha, beta: the two-population fiducial of Section 5
+FIDUCIAL2 = (70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -81,6 +85,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-walker form")
     ap.add_argument("--no-velocity", action="store_true",
                     help="skip the variant with the velocity-gradient factor of eq. (4)")
+    ap.add_argument("--no-two-population", action="store_true",
+                    help="skip the variant with the two-population efficiency of eq. (9)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -253,6 +259,42 @@ def main():
         result["velocity_term"] = {"ms_per_step": round(ms_v, 4), "walker_evals_per_s": round(nw / (ms_v * 1e-3), 2),
                                    "note": "same step with dT_b times H / (dv_r/dr + H), |dv_r/dr| / H <= 0.2"}
         vctx.close()
+
+    if not args.no_two_population:
+        # the same step for two-population walkers (zeta0, R_mfp, T_feed, alpha, beta)
+        # drawn from their priors, against the mock of the fiducial of that model
+        log("timing the two-population variant")
+        walkers2 = synth.draw_walkers2(nw, synth.WALKER_SEEDS["two-population-256"])
+        fid2, _ = ctx.eval_batch2(hs, [FIDUCIAL2])
+        fid2 = fid2.cpu().numpy()
+        for i, h in enumerate(hs):
+            km, _counts = ctx.bins(h)
+            ctx.set_mock(h, km ** 3 * fid2[0, i, : len(km)] / (2 * np.pi ** 2))
+
+        def step2():
+            for h in hs:
+                ctx.resmooth(h)
+            ctx.eval_batch2(hs, walkers2, pk, xhi)
+            ctx.chi2(hs, pk, chi2)
+
+        for _ in range(args.warmup):
+            step2()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step2()
+        torch.cuda.synchronize()
+        ms_2 = (time.perf_counter() - t0) * 1e3 / args.steps
+        prof2 = ctx.profile_read()
+        ctx.profile(False)
+        result["two_population"] = {
+            "ms_per_step": round(ms_2, 4), "walker_evals_per_s": round(nw / (ms_2 * 1e-3), 2),
+            "plan_ms_per_step": round(prof2["plan"]["ms"] / args.steps, 4),
+            "ion_ms_per_step": round(prof2["ion"]["ms"] / args.steps, 4),
+            "chi2_median": round(float(chi2.median()), 4),
+            "note": "eq. (9) walkers drawn from the priors; mock = fiducial (70, 15 Mpc, 10^4.7 K, 4/3, -1/3)"}
 
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on one walker x all boxes")

@@ -94,6 +94,20 @@ typedef struct {
   double t_vir;  /* minimum virial temperature, K > 0       */
 } xs21_walker;
 
+/* One parameter set of the two-population model (Section 5, eq. 9): the
+ * efficiency of a halo of virial temperature T is zeta0 (T / t_feed)^beta for
+ * T >= t_feed, zeta0 (T / t_feed)^alpha for 1e4 K <= T < t_feed, and 0 below
+ * 1e4 K (the atomic-cooling limit, which replaces t_vir as the smallest
+ * ionising halo).  Limits: 0 < zeta0 <= 1e6, 1e4 <= t_feed <= 1e9 K,
+ * |alpha|, |beta| <= 10 (the paper's prior is [-4/3, 10/3] for both). */
+typedef struct {
+  double zeta0;   /* normalisation of the efficiency, > 0             */
+  double r_mfp;   /* mean free path / largest filter, Mpc > 0        */
+  double t_feed;  /* feedback virial temperature, K                  */
+  double alpha;   /* power-law index between 1e4 K and t_feed        */
+  double beta;    /* power-law index above t_feed                    */
+} xs21_walker2;
+
 typedef struct xs21_ctx xs21_ctx;
 typedef int32_t xs21_box;
 
@@ -199,6 +213,25 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
 xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
                              void* x_hi, void* dtb);
 
+/* xs21_eval_batch for two-population walkers (Section 5, eq. 9).  The
+ * criterion of eq. (1) weighs each collapsed halo by its own efficiency:
+ * F(delta_R, R) = integral of zeta(M) over the extended Press-Schechter
+ * conditional mass function between the 1e4 K halo mass and the mass of the
+ * sphere; a cell is fully ionised where F >= 1 at some radius <= r_mfp, else
+ * its ionised fraction is F at the cell radius; a sphere at or above delta_c
+ * counts as one halo of its own mass.  Per (walker, box) a device pass turns
+ * F >= 1 into an interval of delta_R per radius (F rises with delta_R to one
+ * maximum, then falls towards delta_c) and tabulates F at the cell radius
+ * (FP64 quadrature, relative error below 1e-9; the table's interpolation
+ * error is below 1e-7).  Same outputs, layout and errors as
+ * xs21_eval_batch. */
+xs21_status xs21_eval_batch2(xs21_ctx* ctx, const xs21_box* boxes, int nb,
+                             const xs21_walker2* walkers, int nw, double* pk, double* xhi_mean);
+
+/* xs21_materialize for one two-population walker. */
+xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* walker,
+                              void* x_hi, void* dtb);
+
 /* Copies smoothed box `index` of the shared ladder of `box` into `out` (DEVICE,
  * n^3 values of the box dtype, converted from the storage type). Asynchronous. */
 xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out);
@@ -240,7 +273,8 @@ typedef enum {
   XS21_K_ION = 5,        /* per-cell ionisation + dT_b + forward x pass        */
   XS21_K_FINALIZE = 6,   /* FP64 reduction of bin and x_HI partial sums        */
   XS21_K_OTHER = 7,      /* materialisation and casts                          */
-  XS21_K_COUNT = 8
+  XS21_K_PLAN = 8,       /* two-population thresholds and efficiency tables   */
+  XS21_K_COUNT = 9
 } xs21_kernel;
 
 /* enable != 0: from now on every kernel launch of the context is bracketed by

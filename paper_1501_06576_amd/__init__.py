@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxs21.so")
 
 F32, F64, BF16 = 0, 1, 2
-KERNELS = ("rows_r2c", "rows_c2r", "axis_fwd", "axis_inv", "axis_bins", "ion", "finalize", "other")
+KERNELS = ("rows_r2c", "rows_c2r", "axis_fwd", "axis_inv", "axis_bins", "ion", "finalize", "other", "plan")
 _DTYPES = {"f32": F32, "f64": F64, "bf16": BF16}
 
 
@@ -40,6 +40,12 @@ class Physics(ctypes.Structure):
 
 class Walker(ctypes.Structure):
     _fields_ = [("zeta", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_vir", ctypes.c_double)]
+
+
+class Walker2(ctypes.Structure):
+    """Two-population parameter set (zeta0, R_mfp, T_feed, alpha, beta) of eq. (9)."""
+    _fields_ = [("zeta0", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_feed", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -62,6 +68,8 @@ _SIGNATURES = {
     "xs21_eval_batch": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker), _I, _P, _P]),
     "xs21_eval": (_I, [_P, _I, ctypes.POINTER(Walker), _DP, _I, _P, _P, _DP, _DP, _DP, _DP]),
     "xs21_materialize": (_I, [_P, _I, ctypes.POINTER(Walker), _P, _P]),
+    "xs21_eval_batch2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker2), _I, _P, _P]),
+    "xs21_materialize2": (_I, [_P, _I, ctypes.POINTER(Walker2), _P, _P]),
     "xs21_smoothed": (_I, [_P, _I, _I, _P]),
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
     "xs21_resmooth": (_I, [_P, _I, _P]),
@@ -147,9 +155,10 @@ def plan_bins(n: int, n_bins: int) -> np.ndarray:
 
 # ------------------------------------------------------------------ device context
 
-def _walkers_array(walkers) -> Tuple[ctypes.Array, int]:
-    w = np.ascontiguousarray(np.asarray(walkers, dtype=np.float64).reshape(-1, 3))
-    arr = (Walker * len(w))()
+def _walkers_array(walkers, kind=None) -> Tuple[ctypes.Array, int]:
+    kind = kind or Walker
+    w = np.ascontiguousarray(np.asarray(walkers, dtype=np.float64).reshape(-1, len(kind._fields_)))
+    arr = (kind * len(w))()
     ctypes.memmove(arr, w.ctypes.data, w.nbytes)
     return arr, len(w)
 
@@ -236,16 +245,22 @@ class Context:
 
     def eval_batch(self, boxes: Sequence[int], walkers, pk=None, xhi=None):
         """Batched evaluation; returns device tensors pk [nw, nb, nbmax] and xhi [nw, nb] (float64)."""
+        return self._batch(boxes, walkers, pk, xhi, Walker, library().xs21_eval_batch)
+
+    def eval_batch2(self, boxes: Sequence[int], walkers, pk=None, xhi=None):
+        """eval_batch for two-population walkers (zeta0, R_mfp, T_feed, alpha, beta), eq. (9)."""
+        return self._batch(boxes, walkers, pk, xhi, Walker2, library().xs21_eval_batch2)
+
+    def _batch(self, boxes, walkers, pk, xhi, kind, fn):
         torch = self.torch
         bx = (ctypes.c_int32 * len(boxes))(*boxes)
-        warr, nw = _walkers_array(walkers)
+        warr, nw = _walkers_array(walkers, kind)
         nbmax = max(self.boxes[b]["n_bins"] for b in boxes)
         if pk is None:
             pk = torch.empty((nw, len(boxes), nbmax), dtype=torch.float64, device=self.device)
         if xhi is None:
             xhi = torch.empty((nw, len(boxes)), dtype=torch.float64, device=self.device)
-        _check(library().xs21_eval_batch(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()),
-                                         ctypes.c_void_p(xhi.data_ptr())))
+        _check(fn(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()), ctypes.c_void_p(xhi.data_ptr())))
         return pk, xhi
 
     def eval(self, box: int, walker, radii=None, fields=True) -> dict:
@@ -270,15 +285,20 @@ class Context:
 
     def materialize(self, box: int, walker):
         """x_HI and dT_b of one walker from the resident smoothed boxes (device tensors)."""
+        return self._fields(box, Walker(*map(float, walker)), library().xs21_materialize)
+
+    def materialize2(self, box: int, walker):
+        """materialize for one two-population walker (zeta0, R_mfp, T_feed, alpha, beta)."""
+        return self._fields(box, Walker2(*map(float, walker)), library().xs21_materialize2)
+
+    def _fields(self, box, w, fn):
         torch = self.torch
         b = self.boxes[box]
         n = b["n"]
         td = torch.float64 if b["dtype"] == F64 else torch.float32
         x = torch.empty((n, n, n), dtype=td, device=self.device)
         d = torch.empty((n, n, n), dtype=td, device=self.device)
-        w = Walker(*map(float, walker))
-        _check(library().xs21_materialize(self._ctx, box, ctypes.byref(w), ctypes.c_void_p(x.data_ptr()),
-                                          ctypes.c_void_p(d.data_ptr())))
+        _check(fn(self._ctx, box, ctypes.byref(w), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d.data_ptr())))
         return x, d
 
     def smoothed(self, box: int, index: int):

@@ -68,10 +68,41 @@ struct BoxRec {
   size_t spec_bytes() const { return static_cast<size_t>(n) * n * pitch() * 2 * real_size(dtype); }
   int nr() const { return static_cast<int>(radii.size()); }
   size_t wc_size() const { return dtype == xs21::kF64 ? sizeof(WalkerConst<double>) : sizeof(WalkerConst<float>); }
-  size_t table_bytes(int walkers) const {
-    return align_up(walkers * wc_size()) + align_up(static_cast<size_t>(walkers) * xs21::thr_stride() * real_size(dtype));
-  }
+  size_t table_bytes(int walkers) const;
 };
+
+// Walker tables of one box for `cap` walkers of the two-population model:
+// the host writes [WalkerConst][WalkerPlan2][SlotPlan2] (the first `host`
+// bytes), the planning pass writes the thresholds thr[cap][2][stride] and the
+// cell-radius efficiency tables zt[cap][kZetaPitch].
+struct Tab2 {
+  size_t wc = 0, wp = 0, slots = 0, host = 0, thr = 0, zt = 0, total = 0;
+};
+
+Tab2 tab2(const BoxRec& b, int cap) {
+  Tab2 t;
+  const size_t rs = real_size(b.dtype), stride = static_cast<size_t>(xs21::thr_stride());
+  size_t off = 0;
+  t.wc = off;
+  off += align_up(cap * b.wc_size());
+  t.wp = off;
+  off += align_up(cap * sizeof(xs21::WalkerPlan2));
+  t.slots = off;
+  off += align_up(stride * sizeof(xs21::SlotPlan2));
+  t.host = off;
+  t.thr = off;
+  off += align_up(static_cast<size_t>(cap) * 2 * stride * rs);
+  t.zt = off;
+  off += align_up(static_cast<size_t>(cap) * xs21::kZetaPitch * rs);
+  t.total = off;
+  return t;
+}
+
+size_t BoxRec::table_bytes(int walkers) const {
+  const size_t one = align_up(walkers * wc_size()) +
+                     align_up(static_cast<size_t>(walkers) * xs21::thr_stride() * real_size(dtype));
+  return std::max(one, tab2(*this, walkers).total);
+}
 
 struct Layout {
   size_t tw32 = 0, tw64 = 0;
@@ -248,8 +279,10 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     b.off_dR = off;
     off += align_up(static_cast<size_t>(b.nr()) * b.cells() * store_size(b.storage));
     tables += b.table_bytes(max_walkers);
-    one = std::max(one, align_up(sizeof(WalkerConst<double>)) + align_up(xs21::thr_stride() * 8) +
-                            align_up(2 * sizeof(long) * xs21::max_radii()));
+    one = std::max({one,
+                    align_up(sizeof(WalkerConst<double>)) + align_up(xs21::thr_stride() * 8) +
+                        align_up(2 * sizeof(long) * xs21::max_radii()),
+                    tab2(b, 1).total});
     scratch = std::max({scratch, smooth_scratch(b), eval_scratch(b, group), plain_scratch(b, max_plain)});
   }
   (void)c;
@@ -303,6 +336,44 @@ void build_tables(const xs21_physics& p, const BoxRec& b, const xs21_walker* w, 
       fill_walker_table<double>(wp, plain, dst + i * wcs, reinterpret_cast<double*>(thr_base) + i * ts, w[i].zeta);
     else
       fill_walker_table<float>(wp, plain, dst + i * wcs, reinterpret_cast<float*>(thr_base) + i * ts, w[i].zeta);
+  }
+}
+
+// Index of the first ladder radius <= r_mfp (the cell radius if none is).
+int first_radius(const BoxRec& b, double r_mfp) {
+  for (int j = 0; j < b.nr() - 1; ++j)
+    if (b.radii[j] <= r_mfp) return j;
+  return b.nr() - 1;
+}
+
+template <typename T>
+void put_const(unsigned char* dst, double a_cell, int used, bool partial) {
+  WalkerConst<T> c;
+  c.zeta = T(1);   // the efficiency lives in the planned thresholds and table
+  c.a_cell = static_cast<T>(a_cell);
+  c.chunks = (used + 7) / 8;
+  c.partial = partial ? 1 : 0;
+  std::memcpy(dst, &c, sizeof c);
+}
+
+// Host part of the two-population tables of `count` walkers on box b (the
+// shared ladder), written at dst in the Tab2 layout for `cap` walkers.
+void build_tables2(const xs21_physics& p, const BoxRec& b, const xs21_walker2* w, int count, unsigned char* dst,
+                   int cap) {
+  const Tab2 t = tab2(b, cap);
+  const auto slots = xs21::plan::slots2(p, b.z, b.radii);
+  std::memset(dst + t.slots, 0, t.host - t.slots);
+  std::memcpy(dst + t.slots, slots.data(), slots.size() * sizeof(xs21::SlotPlan2));
+  const double ds = slots[0].ds_cool;
+  const double a_cell = ds > 0.0 ? 1.0 / std::sqrt(2.0 * ds) : 0.0;
+  for (int i = 0; i < count; ++i) {
+    const int used = b.nr() - first_radius(b, w[i].r_mfp);
+    if (b.dtype == xs21::kF64)
+      put_const<double>(dst + t.wc + i * b.wc_size(), a_cell, used, ds > 0.0);
+    else
+      put_const<float>(dst + t.wc + i * b.wc_size(), a_cell, used, ds > 0.0);
+    const xs21::WalkerPlan2 wp = xs21::plan::walker2(p, b.z, w[i], used);
+    std::memcpy(dst + t.wp + i * sizeof wp, &wp, sizeof wp);
   }
 }
 
@@ -447,7 +518,7 @@ EvalSlot eval_slot(const BoxRec& b, unsigned char* base, int count) {
 // Ionisation + dT_b + x pass for `count` walkers whose tables are at wc/thr
 // (the ALU-bound stage), on stream st.
 hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlot& sl, const void* dR, int storage,
-                     int nr, const void* wc, const void* thr, int count, double radii_used) {
+                     int nr, const void* wc, const void* thr, const void* zt, int count, double radii_used) {
   const long n = b.n, h = static_cast<long>(b.half());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
@@ -457,7 +528,7 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   return timed(
       c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
       [&] {
-        return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_od, nr, wc, thr, count, tb,
+        return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_od, nr, wc, thr, zt, count, tb,
                                 c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
       },
       ion_ops);
@@ -716,12 +787,18 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
   return XS21_OK;
 }
 
-xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers, int nw,
-                            double* pk, double* xhi_mean) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of xs21_eval_batch (w1) and xs21_eval_batch2 (w2): exactly
+// one walker array is non-null.
+xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* w1,
+                            const xs21_walker2* w2, int nw, double* pk, double* xhi_mean) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
-  if (!boxes || nb < 1 || !walkers || nw < 1) return fail(XS21_EINVAL, "empty batch");
+  if (!boxes || nb < 1 || !(w1 || w2) || nw < 1) return fail(XS21_EINVAL, "empty batch");
   if (nb > static_cast<int>(ctx->boxes.size())) return fail(XS21_EINVAL, "more listed boxes than registered");
   int nbmax = 0;
   for (int i = 0; i < nb; ++i) {
@@ -733,52 +810,88 @@ xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
       if (boxes[k] == boxes[i]) return fail(XS21_EINVAL, "box %d listed twice", boxes[i]);
   }
   for (int w = 0; w < nw; ++w)
-    if (!xs21::plan::valid_walker(walkers[w])) return fail(XS21_EINVAL, "walker %d has invalid parameters", w);
+    if (w1 ? !xs21::plan::valid_walker(w1[w]) : !xs21::plan::valid_walker2(w2[w]))
+      return fail(XS21_EINVAL, "walker %d has invalid parameters", w);
+  auto r_mfp = [&](long w) { return w1 ? w1[w].r_mfp : w2[w].r_mfp; };
 
   const hipStream_t st = ctx->stream;
+  const size_t stride = static_cast<size_t>(xs21::thr_stride());
   for (int w0 = 0; w0 < nw; w0 += ctx->max_walkers) {
     const int cnt = std::min(ctx->max_walkers, nw - w0);
     if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
     // host planning for every (walker, box) of this chunk
     size_t off = 0;
     std::vector<size_t> boff(nb);
+    unsigned char* pin = static_cast<unsigned char*>(ctx->pinned);
     for (int i = 0; i < nb; ++i) {
       const BoxRec& b = ctx->boxes[boxes[i]];
       boff[i] = off;
-      build_tables(ctx->phys, b, walkers + w0, cnt, false, b.radii, static_cast<unsigned char*>(ctx->pinned) + off,
-                   ctx->max_walkers);
+      if (w1)
+        build_tables(ctx->phys, b, w1 + w0, cnt, false, b.radii, pin + off, ctx->max_walkers);
+      else
+        build_tables2(ctx->phys, b, w2 + w0, cnt, pin + off, ctx->max_walkers);
       off += b.table_bytes(ctx->max_walkers);
     }
-    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tables, ctx->pinned, off, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+    if (w1) {
+      HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tables, pin, off, hipMemcpyHostToDevice, st));
+    } else {
+      for (int i = 0; i < nb; ++i)   // only the host-written part of each box's tables
+        HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + ctx->lay.tables + boff[i], pin + boff[i],
+                                     tab2(ctx->boxes[boxes[i]], ctx->max_walkers).host, hipMemcpyHostToDevice, st));
+    }
+    HIPCHECK(ctx, hipEventRecord(ctx->upload_done, st));
     ctx->upload_pending = true;
     for (int i = 0; i < nb; ++i) {
       const BoxRec& b = ctx->boxes[boxes[i]];
-      const unsigned char* wc = ctx->ws + ctx->lay.tables + boff[i];
+      const size_t rs = real_size(b.dtype);
+      unsigned char* base = ctx->ws + ctx->lay.tables + boff[i];
+      const unsigned char* wc = base;
       const unsigned char* thr = wc + align_up(ctx->max_walkers * b.wc_size());
+      const unsigned char* zt = nullptr;
+      size_t thr_w = stride * rs;   // threshold bytes per walker
+      if (w2) {
+        const Tab2 t = tab2(b, ctx->max_walkers);
+        thr = base + t.thr;
+        zt = base + t.zt;
+        thr_w = 2 * stride * rs;
+        HIPCHECK(ctx, timed(ctx, st, XS21_K_PLAN, 0.0, [&] {
+          return xs21::launch_plan2(b.dtype, reinterpret_cast<const xs21::SlotPlan2*>(base + t.slots), b.nr(),
+                                    reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), cnt, base + t.thr,
+                                    static_cast<int>(stride), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c, st);
+        }));
+      }
       for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
         const int g = std::min(ctx->group, cnt - g0);
         const long wg = w0 + g0;
         double used = 0;
-        for (int k = 0; k < g; ++k) {
-          int first = b.nr() - 1;
-          for (int j = 0; j < b.nr() - 1; ++j)
-            if (b.radii[j] <= walkers[wg + k].r_mfp) {
-              first = j;
-              break;
-            }
-          used += b.nr() - first;
-        }
+        for (int k = 0; k < g; ++k) used += b.nr() - first_radius(b, r_mfp(wg + k));
         double* pk_out = pk ? pk + (wg * nb + i) * nbmax : nullptr;
         double* xh_out = xhi_mean ? xhi_mean + wg * nb + i : nullptr;
         const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, g);
         HIPCHECK(ctx, ion_stage(ctx, st, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc + g0 * b.wc_size(),
-                                thr + static_cast<size_t>(g0) * xs21::thr_stride() * real_size(b.dtype), g, used));
+                                thr + static_cast<size_t>(g0) * thr_w,
+                                zt ? zt + static_cast<size_t>(g0) * xs21::kZetaPitch * rs : nullptr, g, used));
         HIPCHECK(ctx, mem_stage(ctx, st, b, sl, g, pk_out, static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
       }
     }
   }
   return XS21_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xs21_status xs21_eval_batch(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers, int nw,
+                            double* pk, double* xhi_mean) {
+  if (!walkers) return fail(XS21_EINVAL, "null walkers");
+  return eval_batch_impl(ctx, boxes, nb, walkers, nullptr, nw, pk, xhi_mean);
+}
+
+xs21_status xs21_eval_batch2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker2* walkers, int nw,
+                             double* pk, double* xhi_mean) {
+  if (!walkers) return fail(XS21_EINVAL, "null walkers");
+  return eval_batch_impl(ctx, boxes, nb, nullptr, walkers, nw, pk, xhi_mean);
 }
 
 xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, const double* radii, int n_radii,
@@ -831,7 +944,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
   // the eval scratch of a plain call sits after the plain smoothed boxes
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   const EvalSlot sl = eval_slot(b, eval_area, 1);
-  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, dR, b.dtype, nr, wc, thr, 1, nr));
+  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, dR, b.dtype, nr, wc, thr, nullptr, 1, nr));
   HIPCHECK(ctx, mem_stage(ctx, ctx->stream, b, sl, 1, outs, b.nbins, b.nbins, outs + 128, 1));
   if (x_hi || dtb) {
     // fields through the same per-cell arithmetic; staged in the hat/tmp area
@@ -842,7 +955,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
     void* fd = hat + align_up(fbytes);
     const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
     HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_od, nr, wc, thr, tbv,
+      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_od, nr, wc, thr, nullptr, tbv,
                                       ctx->phys.delta_c, fx, fd, ctx->stream);
     }));
     if (x_hi) HIPCHECK(ctx, hipMemcpyAsync(x_hi, fx, fbytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -876,7 +989,36 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
   HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
     return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_od, b.nr(), wc,
-                                    wc + align_up(b.wc_size()), tbv, ctx->phys.delta_c, x_hi, dtb, ctx->stream);
+                                    wc + align_up(b.wc_size()), nullptr, tbv, ctx->phys.delta_c, x_hi, dtb,
+                                    ctx->stream);
+  }));
+  return XS21_OK;
+}
+
+xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* walker, void* x_hi, void* dtb) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!walker || !xs21::plan::valid_walker2(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  const BoxRec& b = ctx->boxes[box];
+  if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
+  build_tables2(ctx->phys, b, walker, 1, static_cast<unsigned char*>(ctx->pinned), 1);
+  const Tab2 t = tab2(b, 1);
+  unsigned char* base = ctx->ws + ctx->lay.one_table;
+  HIPCHECK(ctx, hipMemcpyAsync(base, ctx->pinned, t.host, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+  ctx->upload_pending = true;
+  HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_PLAN, 0.0, [&] {
+    return xs21::launch_plan2(b.dtype, reinterpret_cast<const xs21::SlotPlan2*>(base + t.slots), b.nr(),
+                              reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), 1, base + t.thr,
+                              xs21::thr_stride(), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c, ctx->stream);
+  }));
+  const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
+  HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
+    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_od, b.nr(),
+                                    base + t.wc, base + t.thr, base + t.zt, tbv, ctx->phys.delta_c, x_hi, dtb,
+                                    ctx->stream);
   }));
   return XS21_OK;
 }

@@ -92,4 +92,27 @@ struct WalkerConst {
   int32_t partial;  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged
 };
 
+// Two-population efficiency of eq. (9): radius-slot constants (walker
+// independent) and walker inputs of the device planning pass, FP64.
+struct SlotPlan2 {
+  double s_r;       // sigma^2(R)
+  double ds_cool;   // sigma^2(M_cool) - sigma^2(R), M_cool the 1e4 K halo mass; <= 0: F = 0
+  double lny_r;     // ln y at R, y = (k_c / k0)^2 (halo mass ~ y^-3/2)
+  double lam_a;     // quadrature range in ln(S - S_R): from lam_a ...
+  double lam_b;     // ... to lam_b = ln(ds_cool)
+  double cvar;      // c of sigma^2 = c (ln(1 + y) - y / (1 + y))
+};
+struct WalkerPlan2 {
+  double zeta0, alpha, beta;
+  double lny_f;     // ln y of the feedback mass M(T_feed)
+  double s_f;       // sigma^2(M(T_feed))
+  int32_t used;     // radius slots the walker filters at (from the cell radius up)
+  int32_t pad;
+};
+// Effective-efficiency table of the cell radius: entry k holds F / erfc(t) at
+// t = (k h)^2, h = sqrt(t_max) / (kZetaTab - 1); rows are kZetaPitch long.
+constexpr int kZetaTab = 1025;
+constexpr int kZetaPitch = 1032;
+constexpr double kZetaTmax = 8.0;
+
 }  // namespace xs21

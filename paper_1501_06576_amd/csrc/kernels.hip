@@ -528,9 +528,29 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
 // walker's last used group (a wave-uniform exit), so the compares follow the
 // walker's own radius count and its threshold loads batch into wide scalar
 // loads.  Unflagged cells keep x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)).
+//
+// TWO (the two-population efficiency of Section 5, eq. 9): each slot has an
+// interval, flag iff thr[s] <= delta_R <= thr[NR + s], and unflagged cells
+// keep x_HI = 1 - zeta_eff(t) erfc(t), t = max(a_cell (delta_c - delta_cell), 0),
+// with zeta_eff read from the walker's cell-radius table zt.
 // ---------------------------------------------------------------------------
-template <typename T, int NR>
-__device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, T dc) {
+
+// Effective efficiency at t >= 0 from a table of t = (k h)^2, k < kZetaTab:
+// 4-point Lagrange interpolation in sqrt(t), clamped to the table's end.
+template <typename T>
+__device__ __forceinline__ T zeta_eff(const T* __restrict__ tab, T t) {
+  const T inv_h = static_cast<T>((kZetaTab - 1) / 2.8284271247461903);   // 1 / h, h = sqrt(8) / (K - 1)
+  const T u = min(sqrt(t) * inv_h, static_cast<T>(kZetaTab - 1));
+  const int j = min(max(static_cast<int>(u) - 1, 0), kZetaTab - 4);
+  const T x = u - static_cast<T>(j);
+  const T x1 = x - T(1), x2 = x - T(2), x3 = x - T(3);
+  const T p0 = tab[j], p1 = tab[j + 1], p2 = tab[j + 2], p3 = tab[j + 3];
+  return (x * x1 * (p3 * x2 - T(3) * p2 * x3) + x2 * x3 * (T(3) * p1 * x - p0 * x1)) * T(1.0 / 6.0);
+}
+
+template <typename T, int NR, bool TWO>
+__device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, const T* zt_w,
+                                      T dc) {
   static_assert(NR % 8 == 0, "radius slots come in groups of 8");
   // OR over radii as wave-wide lane masks: one compare into a scalar mask per slot
   unsigned long long m = 0;
@@ -538,14 +558,25 @@ __device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c,
   for (int g = 0; g < NR / 8; ++g) {
     if (g >= c.chunks) break;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) m |= __ballot(d[8 * g + k] >= thr_w[8 * g + k]);
+    for (int k = 0; k < 8; ++k) {
+      const int s = 8 * g + k;
+      if constexpr (TWO)
+        m |= __ballot((d[s] >= thr_w[s]) & (d[s] <= thr_w[NR + s]));
+      else
+        m |= __ballot(d[s] >= thr_w[s]);
+    }
   }
   const bool flag = (m >> __lane_id()) & 1ull;
   T x = T(1);
   if (flag) {
     x = T(0);
   } else if (c.partial) {
-    x = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
+    if constexpr (TWO) {
+      const T t = max(c.a_cell * (dc - d[0]), T(0));
+      x = T(1) - zeta_eff(zt_w, t) * erfc_t(t);
+    } else {
+      x = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
+    }
   }
   return x;
 }
@@ -605,11 +636,11 @@ struct IonShape {
 // smoothed boxes are read once per group.  Two real rows are transformed as
 // one complex row.  Output: spec[w][row][kx < N/2] (streaming stores), the
 // Nyquist plane nyq[w][y][z], and per-block x_HI sums xpart[w][block].
-template <typename T, typename S, int N>
+template <typename T, typename S, int N, bool TWO>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ odens, int nr, const WalkerConst<T>* __restrict__ wc,
-    const T* __restrict__ thr, int nw, T tb, T dc, cplx<T>* __restrict__ spec, cplx<T>* __restrict__ nyq,
-    double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride) {
+    const T* __restrict__ thr, const T* __restrict__ zt, int nw, T tb, T dc, cplx<T>* __restrict__ spec,
+    cplx<T>* __restrict__ nyq, double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride) {
   using IS = IonShape<N>;
   constexpr size_t N3 = static_cast<size_t>(N) * N * N;
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
@@ -635,7 +666,8 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        const T xh = cell_xhi<T, kNrMax>(d, wc[w], thr + static_cast<size_t>(w) * kNrMax, dc);
+        const T xh = cell_xhi<T, kNrMax, TWO>(d, wc[w], thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
+                                              zt + static_cast<size_t>(w) * kZetaPitch, dc);
         ldsr[2 * (q * N + x) + row] = tb * xh * od;
         if constexpr (IS::NT >= 64) {
           const T s = row_sum(xh);
@@ -690,18 +722,18 @@ __global__ __launch_bounds__(256) void k_los_factor(const T* __restrict__ delta,
 }
 
 // Materialise x_HI and dT_b of one walker (same per-cell arithmetic as above).
-template <typename T, typename S, int N>
+template <typename T, typename S, int N, bool TWO>
 __global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, const T* __restrict__ odens, int nr,
                                                      const WalkerConst<T>* __restrict__ wc,
-                                                     const T* __restrict__ thr, T tb, T dc, T* __restrict__ xhi,
-                                                     T* __restrict__ dtb) {
+                                                     const T* __restrict__ thr, const T* __restrict__ zt, T tb,
+                                                     T dc, T* __restrict__ xhi, T* __restrict__ dtb) {
   constexpr size_t N3 = static_cast<size_t>(N) * N * N;
   const WalkerConst<T> c = wc[0];
   for (size_t cell = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; cell < N3;
        cell += static_cast<size_t>(gridDim.x) * 256) {
     T d[kNrMax];
     load_radii<T, S>(dR, N3, cell, nr, d);
-    const T x = cell_xhi<T, kNrMax>(d, c, thr, dc);
+    const T x = cell_xhi<T, kNrMax, TWO>(d, c, thr, zt, dc);
     if (xhi) xhi[cell] = x;
     if (dtb) dtb[cell] = tb * x * odens[cell];
   }
@@ -978,8 +1010,8 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, 
 }
 
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
-                      const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
-                      const void* tw, int ntab, hipStream_t s) {
+                      const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
+                      double* xpart, const void* tw, int ntab, hipStream_t s) {
   if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
@@ -987,21 +1019,24 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
       using ST = decltype(sv);
       return with_n(n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
-        hipLaunchKernelGGL((k_ion_rows<T, ST, N>), dim3(ion_grid(N)), dim3(IonShape<N>::NT), 0, s,
-                           static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
-                           static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr), nw,
-                           static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec),
-                           static_cast<cplx<T>*>(nyq), xpart,
-                           static_cast<const cplx<T>*>(tw), ntab / N);
-        return hipGetLastError();
+        auto go = [&](auto two) {
+          hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value>), dim3(ion_grid(N)), dim3(IonShape<N>::NT),
+                             0, s, static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
+                             static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr),
+                             static_cast<const T*>(zt), nw, static_cast<T>(tb), static_cast<T>(dc),
+                             static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,
+                             static_cast<const cplx<T>*>(tw), ntab / N);
+          return hipGetLastError();
+        };
+        return zt ? go(std::true_type{}) : go(std::false_type{});
       });
     });
   });
 }
 
 hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
-                              const void* wc, const void* thr, double tb, double dc, void* xhi, void* dtb,
-                              hipStream_t s) {
+                              const void* wc, const void* thr, const void* zt, double tb, double dc, void* xhi,
+                              void* dtb, hipStream_t s) {
   if (nr < 1 || nr > kNrMax) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
@@ -1010,11 +1045,15 @@ hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, con
       return with_n(n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
         const long cells = static_cast<long>(N) * N * N;
-        hipLaunchKernelGGL((k_materialize<T, ST, N>), dim3(grid_for((cells + 255) / 256, 16384)), dim3(256), 0, s,
-                           static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
-                           static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr),
-                           static_cast<T>(tb), static_cast<T>(dc), static_cast<T*>(xhi), static_cast<T*>(dtb));
-        return hipGetLastError();
+        auto go = [&](auto two) {
+          hipLaunchKernelGGL((k_materialize<T, ST, N, decltype(two)::value>),
+                             dim3(grid_for((cells + 255) / 256, 16384)), dim3(256), 0, s, static_cast<const ST*>(dR),
+                             static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc),
+                             static_cast<const T*>(thr), static_cast<const T*>(zt), static_cast<T>(tb),
+                             static_cast<T>(dc), static_cast<T*>(xhi), static_cast<T*>(dtb));
+          return hipGetLastError();
+        };
+        return zt ? go(std::true_type{}) : go(std::false_type{});
       });
     });
   });

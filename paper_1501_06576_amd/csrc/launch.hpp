@@ -55,13 +55,24 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, 
                             const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s);
 // Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
 // [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
+// zt == nullptr: constant efficiency, thr[w][max_radii()]; else the
+// two-population efficiency, thr[w][2][max_radii()] (lo, hi) and the cell
+// radius tables zt[w][kZetaPitch] written by launch_plan2.
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
-                      const void* thr, int nw, double tb, double dc, void* spec, void* nyq, double* xpart,
-                      const void* tw, int ntab, hipStream_t s);
-// x_HI and dT_b boxes of one walker (either output may be null).
+                      const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
+                      double* xpart, const void* tw, int ntab, hipStream_t s);
+// x_HI and dT_b boxes of one walker (either output may be null); zt as above.
 hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
-                              const void* wc, const void* thr, double tb, double dc, void* xhi, void* dtb,
-                              hipStream_t s);
+                              const void* wc, const void* thr, const void* zt, double tb, double dc, void* xhi,
+                              void* dtb, hipStream_t s);
+// Two-population planning (Section 5, eq. 9) of nw walkers on one box:
+// slots[nr] (device, slot 0 = cell radius), wp[nw] (device) -> thresholds
+// thr[w][2][stride] (lo, hi; +inf where unused) and the cell-radius
+// effective-efficiency tables zt[w][pitch], in `dtype`.
+struct SlotPlan2;
+struct WalkerPlan2;
+hipError_t launch_plan2(int dtype, const SlotPlan2* slots, int nr, const WalkerPlan2* wp, int nw, void* thr,
+                        int stride, void* zt, int pitch, double dc, hipStream_t s);
 // Deterministic reduction of the bin and x_HI partial sums, one walker per block.
 hipError_t launch_finalize(int nwalkers, const double* part, long ntiles, int nbins, const double* xpart, long nblk,
                            const double* counts, double pscale, double inv_cells, double* pk, long pk_stride,

@@ -48,6 +48,12 @@ bool valid_physics(const xs21_physics& p) {
 
 bool valid_walker(const xs21_walker& w) { return finite_pos(w.zeta) && finite_pos(w.r_mfp) && finite_pos(w.t_vir); }
 
+bool valid_walker2(const xs21_walker2& w) {
+  return finite_pos(w.zeta0) && w.zeta0 <= 1e6 && finite_pos(w.r_mfp) && std::isfinite(w.t_feed) &&
+         w.t_feed >= 1e4 && w.t_feed <= 1e9 && std::isfinite(w.alpha) && std::fabs(w.alpha) <= 10.0 &&
+         std::isfinite(w.beta) && std::fabs(w.beta) <= 10.0;
+}
+
 std::vector<double> ladder(double r_top, double r_cell, double step) {
   std::vector<double> out;
   for (int i = 0;; ++i) {
@@ -132,6 +138,42 @@ WalkerPlan walker(const xs21_physics& p, double z, const double* radii, int nr, 
   out.partial = dc > 0.0;
   out.a_cell = out.partial ? 1.0 / std::sqrt(2.0 * dc) : 0.0;
   return out;
+}
+
+namespace {
+// ln y, y = (k_c(R) / k0)^2: halo mass ~ R^3 ~ y^-3/2
+double lny_of_radius(const xs21_physics& p, double radius) { return 2.0 * std::log(cutoff(radius) / p.pk_k0); }
+}  // namespace
+
+std::vector<SlotPlan2> slots2(const xs21_physics& p, double z, const std::vector<double>& radii) {
+  const int nr = static_cast<int>(radii.size());
+  const double d = (1.0 + p.z_ref) / (1.0 + z);
+  const double cvar = d * d * p.pk_amp * std::pow(p.pk_k0, 4) / (4.0 * kPi * kPi);
+  const double s_cool = sigma2(p, radius_of_mass(p, min_mass(p, 1e4, z)), z);
+  std::vector<SlotPlan2> out(nr);
+  for (int s = 0; s < nr; ++s) {
+    const double r = radii[nr - 1 - s];
+    SlotPlan2& o = out[s];
+    o.s_r = sigma2(p, r, z);
+    o.ds_cool = s_cool - o.s_r;
+    o.lny_r = lny_of_radius(p, r);
+    o.lam_a = std::log(o.s_r) - 32.0;
+    o.lam_b = o.ds_cool > 0.0 ? std::log(o.ds_cool) : o.lam_a;
+    o.cvar = cvar;
+  }
+  return out;
+}
+
+WalkerPlan2 walker2(const xs21_physics& p, double z, const xs21_walker2& w, int used) {
+  WalkerPlan2 o{};
+  o.zeta0 = w.zeta0;
+  o.alpha = w.alpha;
+  o.beta = w.beta;
+  const double rf = radius_of_mass(p, min_mass(p, w.t_feed, z));
+  o.lny_f = lny_of_radius(p, rf);
+  o.s_f = sigma2(p, rf, z);
+  o.used = used;
+  return o;
 }
 
 std::vector<int8_t> bins(int n, int nbins) {

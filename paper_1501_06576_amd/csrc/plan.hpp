@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/xs21.h"
+#include "common.hpp"
 
 namespace xs21 {
 namespace plan {
@@ -55,8 +56,15 @@ void bin_stats(int n, int nbins, double box, const std::vector<int8_t>& table, s
 // Forward twiddles exp(-2 pi i m / ntab), m in [0, ntab), interleaved (re, im).
 std::vector<double> twiddles(int ntab);
 
+// Two-population efficiency (Section 5, eq. 9): walker-independent constants
+// of each radius slot of a ladder (slot s = radius nr - 1 - s, slot 0 the cell
+// radius), and one walker's inputs of the device planning pass.
+std::vector<SlotPlan2> slots2(const xs21_physics& p, double z, const std::vector<double>& radii);
+WalkerPlan2 walker2(const xs21_physics& p, double z, const xs21_walker2& w, int used);
+
 bool valid_physics(const xs21_physics& p);
 bool valid_walker(const xs21_walker& w);
+bool valid_walker2(const xs21_walker2& w);
 
 }  // namespace plan
 }  // namespace xs21

@@ -33,11 +33,15 @@ REF_GRID = (64, 128.0)  # (N, L / Mpc) of the reference grid
 
 # Seeds: one density realisation per geometry, one walker draw per batch.
 BOX_SEEDS = {(64, 128.0): 1, (128, 250.0): 2, (256, 250.0): 3, (256, 300.0): 4, (512, 400.0): 5}
-WALKER_SEEDS = {"batched-256": 103, "uneven-mix": 104, "large-512": 105}
+WALKER_SEEDS = {"batched-256": 103, "uneven-mix": 104, "large-512": 105, "two-population-256": 106}
 
 # Uniform priors (paper Section 2.1 ranges for zeta and R_mfp; log10 T_vir in [4, 6]).
 PRIOR_LO = (5.0, 5.0, 4.0)
 PRIOR_HI = (100.0, 20.0, 6.0)
+# two-population walkers (zeta0, R_mfp, log10 T_feed, alpha, beta): the ranges
+# of Section 2.1 for the first three and [-4/3, 10/3] for both indices (Section 5)
+PRIOR2_LO = (5.0, 5.0, 4.0, -4.0 / 3.0, -4.0 / 3.0)
+PRIOR2_HI = (100.0, 20.0, 5.301029995663981, 10.0 / 3.0, 10.0 / 3.0)
 
 
 def growth(z: float) -> float:
@@ -103,6 +107,17 @@ def draw_walkers(count: int, seed: int) -> np.ndarray:
     u = rng.uniform(low=PRIOR_LO, high=PRIOR_HI, size=(count, 3))
     out = u.copy()
     out[:, 2] = 10.0 ** u[:, 2]
+    return out
+
+
+def draw_walkers2(count: int, seed: int) -> np.ndarray:
+    """(count, 5) float64 array of (zeta0, R_mfp / Mpc, T_feed / K, alpha, beta) from uniform priors.
+
+    Each row draws zeta0, R_mfp, log10 T_feed, alpha and beta in that order.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = rng.uniform(low=PRIOR2_LO, high=PRIOR2_HI, size=(count, 5))
+    out[:, 2] = 10.0 ** out[:, 2]
     return out
 
 

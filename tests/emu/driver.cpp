@@ -10,11 +10,14 @@
 //   max_plain R
 //   box <file> <dtype f32|f64> <n> <L> <z> <nbins>
 //   walker <zeta> <r_mfp> <t_vir>
+//   walker2 <zeta0> <r_mfp> <t_feed> <alpha> <beta>
 //   out <dir>
 //   prepare
 //   batch                      -> batch_pk.bin [nw][nb][nbmax] f64, batch_xhi.bin [nw][nb] f64
 //   plain <box> <walker> [radii file|-]  -> plain_b{b}_w{w}_{xhi,dtb,pk,xm}.bin
 //   materialize <box> <walker> -> mat_b{b}_w{w}_{xhi,dtb}.bin
+//   batch2 <nbmax> [tag]       -> batch2<tag>_{pk,xhi}.bin for the walker2 list
+//   materialize2 <box> <walker2> -> mat2_b{b}_w{w}_{xhi,dtb}.bin
 //   smoothed <box> <index>     -> sm_b{b}_j{j}.bin
 //   pk <box> <field file>      -> fpk_b{b}.bin
 #include <cstdio>
@@ -59,6 +62,7 @@ int main(int argc, char** argv) {
   xs21_dtype storage = XS21_F32;
   int max_walkers = 8, max_plain = 40;
   std::vector<xs21_walker> walkers;
+  std::vector<xs21_walker2> walkers2;
   std::vector<int> box_dtype, box_n;
   std::vector<std::vector<char>> box_data;
   std::list<std::vector<char>> staged;  // inputs of queued device work, kept to the end
@@ -95,6 +99,35 @@ int main(int argc, char** argv) {
       xs21_walker w;
       is >> w.zeta >> w.r_mfp >> w.t_vir;
       walkers.push_back(w);
+    } else if (cmd == "walker2") {
+      xs21_walker2 w;
+      is >> w.zeta0 >> w.r_mfp >> w.t_feed >> w.alpha >> w.beta;
+      walkers2.push_back(w);
+    } else if (cmd == "batch2") {
+      const int nb = static_cast<int>(box_n.size());
+      std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
+      int nbmax = 0;
+      std::string tag;
+      is >> nbmax >> tag;
+      const int nw = static_cast<int>(walkers2.size());
+      std::vector<double> pk(static_cast<size_t>(nw) * nb * nbmax, -1.0), xm(static_cast<size_t>(nw) * nb, -1.0);
+      CHECK(xs21_eval_batch2(ctx, bx.data(), nb, walkers2.data(), nw, pk.data(), xm.data()));
+      CHECK(xs21_sync(ctx));
+      write_file(out + "/batch2" + tag + "_pk.bin", pk.data(), pk.size() * 8);
+      write_file(out + "/batch2" + tag + "_xhi.bin", xm.data(), xm.size() * 8);
+    } else if (cmd == "materialize2") {
+      int b, w;
+      is >> b >> w;
+      const size_t cells = static_cast<size_t>(box_n[b]) * box_n[b] * box_n[b];
+      const size_t rs = box_dtype[b] == XS21_F64 ? 8 : 4;
+      std::vector<char> xhi(cells * rs), dtb(cells * rs);
+      CHECK(xs21_materialize2(ctx, b, &walkers2[w], xhi.data(), dtb.data()));
+      CHECK(xs21_sync(ctx));
+      char pre[512];
+      std::snprintf(pre, sizeof pre, "%s/mat2_b%d_w%d_", out.c_str(), b, w);
+      write_file(std::string(pre) + "xhi.bin", xhi.data(), xhi.size());
+      write_file(std::string(pre) + "dtb.bin", dtb.data(), dtb.size());
     } else if (cmd == "box") {
       if (!ctx) CHECK(xs21_create(&ctx, 0, nullptr, &phys));
       std::string file, dt;

@@ -34,6 +34,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __constant__
 
 typedef int hipError_t;
 enum {

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 EMU = os.path.join(HERE, "emu")
 BIN = os.path.join(EMU, "_build", "xs21_emu")
 SRC = [os.path.join(ROOT, "paper_1501_06576_amd", "csrc", f)
-       for f in ("kernels.hip", "likelihood.hip", "api.cpp", "plan.cpp")]
+       for f in ("kernels.hip", "likelihood.hip", "two_population.hip", "api.cpp", "plan.cpp")]
+NHIP = 3   # leading SRC entries that are HIP sources (compiled as C++ here)
 EXTRA = [os.path.join(EMU, "emu_runtime.cpp"), os.path.join(EMU, "driver.cpp")]
 
 
@@ -41,7 +42,7 @@ def build() -> str:
     # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 1 bin per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
            "-DXS21_PIPE_BLOCKS=3", "-DXS21_BINS_LDS_BUDGET=17664",
-           "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", SRC[0], SRC[1], "-x", "none", *SRC[2:], *EXTRA,
+           "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", *SRC[:NHIP], "-x", "none", *SRC[NHIP:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -61,6 +62,7 @@ class EmuRun:
             self.lines.append(f"phys {k} {v!r}")
         self.boxes = []
         self.walkers = []
+        self.walkers2 = []
 
     def box(self, delta: np.ndarray, box_mpc: float, z: float, nbins: int):
         i = len(self.boxes)
@@ -75,6 +77,11 @@ class EmuRun:
         self.lines.append(f"walker {zeta!r} {r_mfp!r} {t_vir!r}")
         self.walkers.append((zeta, r_mfp, t_vir))
         return len(self.walkers) - 1
+
+    def walker2(self, zeta0, r_mfp, t_feed, alpha, beta):
+        self.lines.append(f"walker2 {zeta0!r} {r_mfp!r} {t_feed!r} {alpha!r} {beta!r}")
+        self.walkers2.append((zeta0, r_mfp, t_feed, alpha, beta))
+        return len(self.walkers2) - 1
 
     def cmd(self, line: str):
         self.lines.append(line)

@@ -226,3 +226,44 @@ def test_emu_velocity_factor():
     phys = oracle.Physics(pk_amp=AMP, velocity=True, dvdr_max=0.2)
     run, boxes = _run("f64", specs, EDGE[:3], 2, np.float64, phys={"pk_amp": AMP, "velocity": 1, "dvdr_max": 0.2})
     _check(run, boxes, specs, EDGE[:3], 1e-11, 0.0, phys=phys)
+
+
+# two-population walkers (zeta0, R_mfp, T_feed, alpha, beta) of Section 5
+EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 5
+         (30.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0),        # falls below 1 towards delta_c: bounded intervals
+         (12.0, 8.0, 3e4, -4.0 / 3.0, 2.0),
+         (25.0, 10.0, 2e5, 0.0, 0.0),                      # constant efficiency above 1e4 K
+         (0.4, 12.0, 2e4, 1.0, 0.0),                       # F < 1 everywhere
+         (200.0, 3.0, 1e6, 2.0, 3.0),
+         (60.0, 0.5, 3e4, 1.0, -1.0)]                      # R_mfp below every ladder radius
+
+
+def test_emu_two_population():
+    # one box, six walkers in chunks of 4 (ragged), two materialised; the cell
+    # (0.75 Mpc) holds more than the 1e4 K halo mass
+    specs = [(16, 12.0, 8.0, 4)]
+    walkers = EDGE2[:5] + EDGE2[6:]
+    run = eh.EmuRun(storage="f64", max_walkers=4, phys={"pk_amp": AMP})
+    n, box, z, nb = specs[0]
+    d = synth.make_box(n, box, z, seed=80, amp=AMP, dtype=np.float64)
+    run.box(d, box, z, nb)
+    for w in walkers:
+        run.walker2(*w)
+    run.cmd("prepare")
+    run.cmd(f"batch2 {nb}")
+    for wi in (0, 1):
+        run.cmd(f"materialize2 0 {wi}")
+    run.run()
+    pk = run.read("batch2_pk.bin", np.float64, (len(walkers), 1, nb))
+    xm = run.read("batch2_xhi.bin", np.float64, (len(walkers), 1))
+    shared = oracle.shared_radii(n, box, PHYS)
+    for wi, w in enumerate(walkers):
+        ev = oracle.two_population.evaluate(d, box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+        ok = ev.counts > 0
+        np.testing.assert_allclose(pk[wi, 0][ok], ev.pk[ok], rtol=1e-6, atol=1e-6 * ev.pk[ok].max())
+        assert xm[wi, 0] == pytest.approx(ev.xhi_mean, abs=2e-7)
+        if wi in (0, 1):
+            x = run.read(f"mat2_b0_w{wi}_xhi.bin", np.float64, (n, n, n))
+            same = (x == 0) == ev.flagged
+            assert np.mean(~same) == 0.0
+            assert np.abs(x - ev.x_hi)[same].max() <= 2e-7

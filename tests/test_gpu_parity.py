@@ -412,3 +412,95 @@ def test_velocity_factor(xs, dtype):
     tol = 1e-8 if dtype == "f64" else 2e-3
     assert np.abs(out["dtb"] - ev.dtb)[same].max() <= tol * np.abs(ev.dtb).max()
     ctx.close()
+
+
+# ------------------------------------------------------------------ two-population efficiency (eq. 9)
+
+EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 5
+         (30.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0),        # bounded flag intervals
+         (12.0, 8.0, 3e4, -4.0 / 3.0, 2.0),
+         (25.0, 10.0, 2e5, 0.0, 0.0),                      # constant efficiency above 1e4 K
+         (0.4, 12.0, 2e4, 1.0, 0.0),                       # F < 1 everywhere
+         (200.0, 3.0, 1e6, 2.0, 3.0),
+         (60.0, 0.5, 3e4, 1.0, -1.0)]                      # R_mfp below every ladder radius
+_ORACLE2 = {}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_population_vs_oracle(xs, dtype):
+    """32^3, 64 Mpc, z = 8.5: every edge walker against the oracle (chunks of 3, ragged)."""
+    n, box, z, nb = 32, 64.0, 8.5, 6
+    d32 = synth.make_box(n, box, z, seed=43, amp=AMP, dtype=np.float32)   # same values for both dtypes
+    d = d32.astype(np.float64) if dtype == "f64" else d32
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare(dtype, max_walkers=3, max_plain_radii=30)
+    pk, xhi = ctx.eval_batch2([b], EDGE2)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    shared = ctx.radii(b)
+    for i, w in enumerate(EDGE2):
+        if i not in _ORACLE2:
+            _ORACLE2[i] = oracle.two_population.evaluate(d32.astype(np.float64), box, z, w,
+                                                         oracle.walker_radii(shared, w[1]), nb, PHYS)
+        ev = _ORACLE2[i]
+        x, _ = ctx.materialize2(b, w)
+        x = x.cpu().numpy()
+        flips, rel = report(f"two-pop-{dtype} w{i}", x, ev, pk[i, 0], xhi[i, 0])
+        same = (x == 0) == ev.flagged
+        if dtype == "f64":
+            # quadrature and table interpolation: x_HI within 2e-7
+            assert flips == 0.0 and rel <= 1e-6
+            assert np.abs(x - ev.x_hi)[same].max() <= 2e-7
+            assert abs(xhi[i, 0] - ev.xhi_mean) <= 2e-7
+        else:
+            assert flips <= 1e-4 and rel <= 1e-3
+            assert np.abs(x - ev.x_hi)[same].max() <= 2e-5
+            assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-4
+    ctx.close()
+
+
+def test_two_population_256_sampled(xs):
+    """The benchmark geometry (256^3 x 3 z, 64 walkers per launch) with drawn two-population
+    walkers: flags and x_HI of sampled cells against the oracle cell by cell, and the
+    returned P(k) and mean x_HI against the estimator applied to the materialised field."""
+    wl = synth.WORKLOADS["batched-256"]
+    boxes = synth.workload_boxes(wl, AMP)
+    walkers = synth.draw_walkers2(64, synth.WALKER_SEEDS["two-population-256"])
+    ctx = _ctx(xs)
+    hs = [ctx.add_box(dd, s.box_mpc, s.z, s.n_bins) for dd, s in zip(boxes, wl.boxes)]
+    ctx.prepare("f32", max_walkers=64, max_plain_radii=40)
+    pk, xhi = ctx.eval_batch2(hs, walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    assert np.isfinite(pk).all() and np.all((xhi >= 0) & (xhi <= 1))
+    n, box, z = 256, 250.0, 9.0
+    shared = ctx.radii(hs[1])
+    dh = np.fft.rfftn(boxes[1].astype(np.float64))
+    rng = np.random.default_rng(9)
+    cells = rng.integers(0, n, size=(20000, 3))
+    sampled = {}   # delta_R at the sampled cells, one smoothing per ladder radius
+    for r in shared:
+        sampled[r] = oracle.smooth(dh, n, box, r)[cells[:, 0], cells[:, 1], cells[:, 2]]
+    del dh
+    for i in (7, 29):
+        w = tuple(float(v) for v in walkers[i])
+        flag = np.zeros(len(cells), dtype=bool)
+        f_cell = None
+        for r in oracle.walker_radii(shared, w[1]):
+            f = oracle.two_population.ionizing_fraction(sampled[r], r, z, w, PHYS)
+            flag |= f >= 1.0
+            f_cell = f
+        x_ref = np.where(flag, 0.0, 1.0 - f_cell)
+        x, t = ctx.materialize2(hs[1], w)
+        x = x.cpu().numpy()
+        xs_ = x[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+        same = (xs_ == 0) == flag
+        print(f"[two-pop-256 w{i}] sampled flips={np.mean(~same):.2e} "
+              f"max|dx_HI|={np.abs(xs_ - x_ref)[same].max():.2e}", flush=True)
+        assert np.mean(~same) <= 1e-4
+        assert np.abs(xs_ - x_ref)[same].max() <= 2e-5
+        p_ref = oracle.power_spectrum(t.cpu().numpy(), box, 15)[0]
+        np.testing.assert_allclose(pk[i, 1], p_ref, rtol=2e-4)
+        assert abs(xhi[i, 1] - float(np.mean(x, dtype=np.float64))) <= 1e-5
+    ctx.close()
