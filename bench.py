@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations per second.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FIDUCIAL = (30.0, 15.0, 5e4)  # zeta, R_mfp [Mpc], T_vir [K] of the mock
-# zeta0, R_mfp [Mpc], T_feed [K], alpha, beta: the two-population fiducial of Section 5
+# zeta0, R_mfp [Mpc], T_feed [K], alpha, beta: the two-population fiducial of Section 4
 FIDUCIAL2 = (70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 

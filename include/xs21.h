@@ -94,7 +94,7 @@ typedef struct {
   double t_vir;  /* minimum virial temperature, K > 0       */
 } xs21_walker;
 
-/* One parameter set of the two-population model (Section 5, eq. 9): the
+/* One parameter set of the two-population model (Section 4, eq. 9): the
  * efficiency of a halo of virial temperature T is zeta0 (T / t_feed)^beta for
  * T >= t_feed, zeta0 (T / t_feed)^alpha for 1e4 K <= T < t_feed, and 0 below
  * 1e4 K (the atomic-cooling limit, which replaces t_vir as the smallest
@@ -213,7 +213,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
 xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
                              void* x_hi, void* dtb);
 
-/* xs21_eval_batch for two-population walkers (Section 5, eq. 9).  The
+/* xs21_eval_batch for two-population walkers (Section 4, eq. 9).  The
  * criterion of eq. (1) weighs each collapsed halo by its own efficiency:
  * F(delta_R, R) = integral of zeta(M) over the extended Press-Schechter
  * conditional mass function between the 1e4 K halo mass and the mass of the
@@ -242,7 +242,7 @@ xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out);
  * doubles.  Synchronous. */
 xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk);
 
-/* Likelihood epilogue (Section 2.5; redshifts combined as in Section 4).
+/* Likelihood epilogue (Section 2.5; redshifts combined as in Section 3.4).
  * Sets the mock observation of `box`: delta2_mock[b] is the mock
  * Delta^2_21 (mK^2) on the box's own bins and noise_sigma[b] its
  * observational noise (mK^2; NULL = none).  A bin is fitted when it has modes

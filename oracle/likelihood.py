@@ -5,7 +5,7 @@ test suite, the smoke check and the benchmark's CPU-baseline leg may import it;
 it shares no code with the GPU path.
 
 What it computes (Section 2.5 of Greig & Mesinger 2015, and the multi-epoch
-combination of Section 4): the model 21 cm power spectrum of a walker is
+combination of Section 3.4): the model 21 cm power spectrum of a walker is
 compared with a mock observation through a chi^2 statistic restricted to
 0.15 <= k <= 1.0 Mpc^-1.  The error of a mock bin is its observational noise
 (thermal noise plus sample variance, here an input: the 21cmSense noise is
@@ -65,7 +65,7 @@ def chi2(delta2_model: Sequence[float], delta2_mock: Sequence[float], noise_sigm
 
 
 def chi2_total(per_redshift: Iterable[float]) -> float:
-    """Multi-epoch statistic: the chi^2 of the redshifts added linearly (Section 4)."""
+    """Multi-epoch statistic: the chi^2 of the redshifts added linearly (Section 3.4)."""
     total = 0.0
     for c in per_redshift:
         total += float(c)

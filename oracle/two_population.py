@@ -1,10 +1,10 @@
-"""FP64 CPU oracle of the two-population ionising efficiency (Section 5, eq. 9).
+"""FP64 CPU oracle of the two-population ionising efficiency (Section 4, eq. 9).
 
 TEST INFRASTRUCTURE ONLY, under the same rules as ``excursion_set``: only the
 test suite, the smoke check and the benchmark's CPU-baseline leg may import it;
 it shares no code with the GPU path.
 
-What it computes.  Section 5 replaces the constant efficiency zeta of eq. (1)
+What it computes.  Section 4 replaces the constant efficiency zeta of eq. (1)
 by a function of the host halo's virial temperature (eq. 9): zeta0 (T/T_feed)^beta
 above the feedback temperature T_feed, zeta0 (T/T_feed)^alpha between the
 atomic-cooling limit 1e4 K and T_feed, and 0 below 1e4 K.  The ionisation
@@ -107,7 +107,7 @@ def _panels(a: float, b: float):
 
 
 def ionizing_fraction(delta_r, radius: float, z: float, walker: Sequence[float], phys: es.Physics):
-    """F(delta_R, R): the efficiency-weighted collapsed fraction of Section 5 (per cell)."""
+    """F(delta_R, R): the efficiency-weighted collapsed fraction of Section 4 (per cell)."""
     d = np.asarray(delta_r, dtype=np.float64)
     s_r = es.mass_variance(radius, z, phys)
     m_cool = es.min_halo_mass(T_COOL, z, phys)

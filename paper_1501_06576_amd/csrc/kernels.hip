@@ -529,7 +529,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
 // walker's own radius count and its threshold loads batch into wide scalar
 // loads.  Unflagged cells keep x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)).
 //
-// TWO (the two-population efficiency of Section 5, eq. 9): each slot has an
+// TWO (the two-population efficiency of Section 4, eq. 9): each slot has an
 // interval, flag iff thr[s] <= delta_R <= thr[NR + s], and unflagged cells
 // keep x_HI = 1 - zeta_eff(t) erfc(t), t = max(a_cell (delta_c - delta_cell), 0),
 // with zeta_eff read from the walker's cell-radius table zt.

@@ -65,7 +65,7 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
 hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
                               const void* wc, const void* thr, const void* zt, double tb, double dc, void* xhi,
                               void* dtb, hipStream_t s);
-// Two-population planning (Section 5, eq. 9) of nw walkers on one box:
+// Two-population planning (Section 4, eq. 9) of nw walkers on one box:
 // slots[nr] (device, slot 0 = cell radius), wp[nw] (device) -> thresholds
 // thr[w][2][stride] (lo, hi; +inf where unused) and the cell-radius
 // effective-efficiency tables zt[w][pitch], in `dtype`.

@@ -1,5 +1,5 @@
 // chi^2 likelihood epilogue on the device (Section 2.5; redshifts added
-// linearly as in Section 4), read from the P(k) that the evaluation writes.
+// linearly as in Section 3.4), read from the P(k) that the evaluation writes.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"

@@ -56,7 +56,7 @@ void bin_stats(int n, int nbins, double box, const std::vector<int8_t>& table, s
 // Forward twiddles exp(-2 pi i m / ntab), m in [0, ntab), interleaved (re, im).
 std::vector<double> twiddles(int ntab);
 
-// Two-population efficiency (Section 5, eq. 9): walker-independent constants
+// Two-population efficiency (Section 4, eq. 9): walker-independent constants
 // of each radius slot of a ladder (slot s = radius nr - 1 - s, slot 0 the cell
 // radius), and one walker's inputs of the device planning pass.
 std::vector<SlotPlan2> slots2(const xs21_physics& p, double z, const std::vector<double>& radii);

@@ -1,4 +1,4 @@
-// Device planning of the two-population efficiency (Section 5, eq. 9).
+// Device planning of the two-population efficiency (Section 4, eq. 9).
 //
 // With zeta a function of halo mass, the ionisation criterion of eq. (1)
 // weighs each collapsed halo by its own efficiency:

@@ -39,7 +39,7 @@ WALKER_SEEDS = {"batched-256": 103, "uneven-mix": 104, "large-512": 105, "two-po
 PRIOR_LO = (5.0, 5.0, 4.0)
 PRIOR_HI = (100.0, 20.0, 6.0)
 # two-population walkers (zeta0, R_mfp, log10 T_feed, alpha, beta): the ranges
-# of Section 2.1 for the first three and [-4/3, 10/3] for both indices (Section 5)
+# of Section 2.1 for the first three and [-4/3, 10/3] for both indices (Section 4)
 PRIOR2_LO = (5.0, 5.0, 4.0, -4.0 / 3.0, -4.0 / 3.0)
 PRIOR2_HI = (100.0, 20.0, 5.301029995663981, 10.0 / 3.0, 10.0 / 3.0)
 

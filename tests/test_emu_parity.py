@@ -228,8 +228,8 @@ def test_emu_velocity_factor():
     _check(run, boxes, specs, EDGE[:3], 1e-11, 0.0, phys=phys)
 
 
-# two-population walkers (zeta0, R_mfp, T_feed, alpha, beta) of Section 5
-EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 5
+# two-population walkers (zeta0, R_mfp, T_feed, alpha, beta) of Section 4
+EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 4
          (30.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0),        # falls below 1 towards delta_c: bounded intervals
          (12.0, 8.0, 3e4, -4.0 / 3.0, 2.0),
          (25.0, 10.0, 2e5, 0.0, 0.0),                      # constant efficiency above 1e4 K

@@ -416,7 +416,7 @@ def test_velocity_factor(xs, dtype):
 
 # ------------------------------------------------------------------ two-population efficiency (eq. 9)
 
-EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 5
+EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 4
          (30.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0),        # bounded flag intervals
          (12.0, 8.0, 3e4, -4.0 / 3.0, 2.0),
          (25.0, 10.0, 2e5, 0.0, 0.0),                      # constant efficiency above 1e4 K

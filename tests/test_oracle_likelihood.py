@@ -1,4 +1,4 @@
-"""Pins of the FP64 chi^2 likelihood oracle (Section 2.5, multi-epoch sum of Section 4).
+"""Pins of the FP64 chi^2 likelihood oracle (Section 2.5, multi-epoch sum of Section 3.4).
 
 Each test fixes the statistic through a route other than its own loop: exact
 special cases (model equal to mock, a uniform fractional offset, noise only),

@@ -1,4 +1,4 @@
-"""Pins of the FP64 two-population oracle (Section 5, eq. 9).
+"""Pins of the FP64 two-population oracle (Section 4, eq. 9).
 
 The efficiency-weighted collapsed fraction F is fixed here through routes that
 do not use the oracle's own quadrature: the closed-form erfc of the constant
@@ -21,7 +21,7 @@ import synth
 es = oracle.excursion_set
 tp = oracle.two_population
 PHYS = oracle.Physics(pk_amp=synth.reference_amplitude())
-FID = (70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0)    # the fiducial of Section 5
+FID = (70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0)    # the fiducial of Section 4
 
 
 def _variances(radius, z, walker=None):
