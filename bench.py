@@ -14,7 +14,8 @@ boxes of the walker's own radii per evaluation), Gcell-R/s, the roofline of the
 dominant kernel (HIP events on the library stream inside the timed steps,
 algorithmic bytes), the FP64 CPU oracle timed on a bounded sample, and the
 same step with the velocity-gradient factor of eq. (4) and with two-population
-walkers (the efficiency of eq. (9)).
+walkers (the efficiency of eq. (9)), and the rate of the device-resident
+ensemble sampler (Section 2.3) driving the same evaluation.
 """
 from __future__ import annotations
 
@@ -85,6 +86,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-walker form")
     ap.add_argument("--no-velocity", action="store_true",
                     help="skip the variant with the velocity-gradient factor of eq. (4)")
+    ap.add_argument("--no-mcmc", action="store_true", help="skip the ensemble-sampler loop")
     ap.add_argument("--no-two-population", action="store_true",
                     help="skip the variant with the two-population efficiency of eq. (9)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -229,6 +231,42 @@ def main():
                      "traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 5),
                      "algorithmic_bytes_per_launch": bytes_launch, "source_hash": kernel_source_hash()},
     }
+
+    if not args.no_mcmc:
+        # the MCMC loop itself: ensemble steps of 2 x nw walkers (stretch move,
+        # device-resident walkers, proposals planned and evaluated on the device)
+        # on the resident boxes, against the same mock
+        log("timing ensemble sampler steps")
+        lo, hi = (5.0, 5.0, 4.0), (100.0, 20.0, 5.3)   # zeta, R_mfp, log10 T_vir
+        spec = xs.sampler(lo, hi)
+        ne = 2 * nw
+        x = torch.tensor(np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * synth.uniforms((ne, 3), 401),
+                         dtype=torch.float64, device="cuda")
+        lp = ctx.mcmc_lnprob(hs, spec, x)
+        acc = torch.zeros(ne, dtype=torch.int32, device="cuda")
+        nsteps = args.warmup + args.steps
+        u = torch.tensor(synth.uniforms((nsteps, 2, nw, 3), 402), dtype=torch.float64, device="cuda")
+        for t in range(args.warmup):
+            ctx.mcmc_step(hs, spec, x, lp, u[t], acc)
+        torch.cuda.synchronize()
+        moved = torch.zeros((), dtype=torch.int64, device="cuda")
+        t0 = time.perf_counter()
+        for t in range(args.warmup, nsteps):
+            ctx.mcmc_step(hs, spec, x, lp, u[t], acc)
+            moved += acc.sum()
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
+        # per kernel class, one more step under the library's event timing
+        ctx.profile(True)
+        ctx.mcmc_step(hs, spec, x, lp, u[nsteps - 1], acc)
+        prof_m = ctx.profile_read()
+        ctx.profile(False)
+        result["mcmc"] = {"walkers": ne, "ms_per_step": round(ms_m, 4),
+                          "walker_evals_per_s": round(ne / (ms_m * 1e-3), 2),
+                          "acceptance": round(float(moved) / (ne * args.steps), 4),
+                          "vs_steady_eval": round((ne / (ms_m * 1e-3)) / (nw / (ms_steady * 1e-3)), 4),
+                          "kernel_ms_per_step": {k: round(v["ms"], 4) for k, v in prof_m.items() if v["launches"]},
+                          "note": "stretch move (a = 2) over (zeta, R_mfp, log10 T_vir) in [5,100]x[5,20]x[4,5.3]"}
 
     if not args.no_velocity:
         # the same step with the velocity-gradient factor H / (dv_r/dr + H) in dT_b

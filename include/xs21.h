@@ -261,6 +261,42 @@ xs21_status xs21_set_mock(xs21_ctx* ctx, xs21_box box, const double* delta2_mock
  * needs a mock (XS21_ESTATE otherwise).  Deterministic FP64; asynchronous. */
 xs21_status xs21_chi2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const double* pk, int nw, double* chi2);
 
+/* ---------------------------------------------------------------- ensemble sampler */
+
+/* The affine invariant ensemble sampler of Section 2.3 (Goodman & Weare
+ * 2010, stretch move, the ensemble moved in two halves) on device-resident
+ * walkers, in the paper's coordinates with temperatures as decimal
+ * logarithms: dim = 3: rows (zeta, r_mfp, log10 t_vir); dim = 5: rows (zeta0,
+ * r_mfp, log10 t_feed, alpha, beta) of the two-population model.  The prior
+ * is uniform on the box lo <= x <= hi (first dim entries), which must lie
+ * inside the valid parameter domain (zeta, r_mfp > 0; for dim = 5 also the
+ * xs21_walker2 limits, 4 <= log10 t_feed <= 9); a is the stretch scale (2 in
+ * the paper's sampler). */
+typedef struct {
+  int dim;
+  double lo[5], hi[5];
+  double a;
+} xs21_sampler;
+
+/* ln p of nw walkers x (DEVICE, [nw][dim] doubles) into lp (DEVICE, nw):
+ * -chi^2 / 2 summed over the listed boxes (each needs xs21_set_mock) inside
+ * the prior, -inf outside.  Walkers are planned and evaluated on the device
+ * by the kernels of xs21_eval_batch / xs21_eval_batch2, in chunks of
+ * max_walkers.  Asynchronous on the context stream. */
+xs21_status xs21_mcmc_lnprob(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_sampler* s,
+                             const double* x, int nw, double* lp);
+
+/* One ensemble step, in place on the device: walkers [0, nw/2) move first,
+ * then [nw/2, nw), each against the other half as it stands.  Walker k takes
+ * partner j = floor(u0 * nw/2) of the other half, z = ((a - 1) u1 + 1)^2 / a,
+ * proposal y = x_j + z (x_k - x_j), and moves (x, lp updated) when
+ * ln u2 < (dim - 1) ln z + ln p(y) - lp[k].  u: DEVICE [2][nw/2][3] uniforms
+ * in [0, 1) (first index: the half moving).  lp must hold ln p of x (from
+ * xs21_mcmc_lnprob or the previous step).  accepted (DEVICE, nw int32, may be
+ * NULL): 1 where the walker moved.  nw must be even and >= 4.  Asynchronous. */
+xs21_status xs21_mcmc_step(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_sampler* s, double* x,
+                           double* lp, int nw, const double* u, int32_t* accepted);
+
 /* ---------------------------------------------------------------- kernel timing */
 
 /* Kernel classes timed by xs21_profile_read. */
@@ -273,7 +309,7 @@ typedef enum {
   XS21_K_ION = 5,        /* per-cell ionisation + dT_b + forward x pass        */
   XS21_K_FINALIZE = 6,   /* FP64 reduction of bin and x_HI partial sums        */
   XS21_K_OTHER = 7,      /* materialisation and casts                          */
-  XS21_K_PLAN = 8,       /* two-population thresholds and efficiency tables   */
+  XS21_K_PLAN = 8,       /* planning on the device (thresholds, tables)        */
   XS21_K_COUNT = 9
 } xs21_kernel;
 

@@ -16,7 +16,8 @@ accepted with probability min(1, z^(d-1) p(Y) / p(X_k)) in d dimensions.  All
 proposals of a half use the other half's positions from before that half
 moves, so the walkers of a half are independent.  Here p is the likelihood of
 21CMMC: ln p = -chi^2 / 2 summed over redshifts inside the prior box and -inf
-outside it (uniform priors, Section 3.2).
+outside it (uniform priors, Section 3.2), over the parameters with the virial
+temperature as its decimal logarithm, as the paper quotes it.
 
 Random numbers are inputs: for every half-step and active walker three
 uniforms in [0, 1): u0 picks the partner, j = floor(u0 n_other); u1 gives

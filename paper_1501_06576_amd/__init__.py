@@ -42,6 +42,23 @@ class Walker(ctypes.Structure):
     _fields_ = [("zeta", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_vir", ctypes.c_double)]
 
 
+class Sampler(ctypes.Structure):
+    """Ensemble sampler settings: dim (3 or 5), uniform prior box lo/hi, stretch scale a."""
+    _fields_ = [("dim", ctypes.c_int), ("lo", ctypes.c_double * 5), ("hi", ctypes.c_double * 5),
+                ("a", ctypes.c_double)]
+
+
+def sampler(lo: Sequence[float], hi: Sequence[float], a: float = 2.0) -> Sampler:
+    """Sampler settings for walkers of len(lo) parameters (3: eq. 1 walkers, 5: eq. 9 walkers)."""
+    s = Sampler()
+    s.dim = len(lo)
+    for i, (a_, b_) in enumerate(zip(lo, hi)):
+        s.lo[i] = float(a_)
+        s.hi[i] = float(b_)
+    s.a = float(a)
+    return s
+
+
 class Walker2(ctypes.Structure):
     """Two-population parameter set (zeta0, R_mfp, T_feed, alpha, beta) of eq. (9)."""
     _fields_ = [("zeta0", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_feed", ctypes.c_double),
@@ -69,6 +86,8 @@ _SIGNATURES = {
     "xs21_eval": (_I, [_P, _I, ctypes.POINTER(Walker), _DP, _I, _P, _P, _DP, _DP, _DP, _DP]),
     "xs21_materialize": (_I, [_P, _I, ctypes.POINTER(Walker), _P, _P]),
     "xs21_eval_batch2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker2), _I, _P, _P]),
+    "xs21_mcmc_lnprob": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Sampler), _P, _I, _P]),
+    "xs21_mcmc_step": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Sampler), _P, _P, _I, _P, _P]),
     "xs21_materialize2": (_I, [_P, _I, ctypes.POINTER(Walker2), _P, _P]),
     "xs21_smoothed": (_I, [_P, _I, _I, _P]),
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
@@ -282,6 +301,25 @@ class Context:
                                    None if dtb is None else dtb.ctypes.data_as(ctypes.c_void_p),
                                    _dptr(pk), _dptr(km), _dptr(cn), ctypes.byref(xm)))
         return {"x_hi": x_hi, "dtb": dtb, "pk": pk, "k_mean": km, "counts": cn, "xhi_mean": xm.value}
+
+    def mcmc_lnprob(self, boxes: Sequence[int], spec: Sampler, x, lp=None):
+        """ln p (-chi^2/2 in the prior, -inf outside) of walkers x (device float64 [nw, dim])."""
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        nw = int(x.shape[0])
+        if lp is None:
+            lp = self.torch.empty(nw, dtype=self.torch.float64, device=self.device)
+        _check(library().xs21_mcmc_lnprob(self._ctx, bx, len(boxes), ctypes.byref(spec),
+                                          ctypes.c_void_p(x.data_ptr()), nw, ctypes.c_void_p(lp.data_ptr())))
+        return lp
+
+    def mcmc_step(self, boxes: Sequence[int], spec: Sampler, x, lp, u, accepted=None):
+        """One stretch-move ensemble step in place on x / lp (device float64); u: device float64
+        [2, nw/2, 3] uniforms; accepted: optional device int32 [nw]."""
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        acc = ctypes.c_void_p(accepted.data_ptr()) if accepted is not None else None
+        _check(library().xs21_mcmc_step(self._ctx, bx, len(boxes), ctypes.byref(spec), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(lp.data_ptr()), int(x.shape[0]),
+                                        ctypes.c_void_p(u.data_ptr()), acc))
 
     def materialize(self, box: int, walker):
         """x_HI and dT_b of one walker from the resident smoothed boxes (device tensors)."""

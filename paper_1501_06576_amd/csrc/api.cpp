@@ -61,6 +61,8 @@ struct BoxRec {
   bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
   size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_od = 0, off_dR = 0, off_like = 0;
+  size_t off_slots = 0;       // SlotPlan2 per radius slot, for planning from device walker parameters
+  xs21::BoxPlan bplan{};      // the box's planning scalars (kernel argument)
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
   size_t half() const { return static_cast<size_t>(n / 2 + 1); }
@@ -109,6 +111,7 @@ struct Layout {
   size_t tables = 0, tables_bytes = 0;     // batched walker tables (all boxes)
   size_t one_table = 0, one_table_bytes = 0;  // single-walker table
   size_t outs = 0;                          // small device outputs (plain / debug)
+  size_t samp = 0, samp_pk = 0;             // sampler: proposals, aux, chi^2; their P(k)
   size_t scratch = 0, scratch_bytes = 0;    // union of smoothing / evaluation / plain scratch
   size_t total = 0;
 };
@@ -272,6 +275,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     off += align_up(b.cut.size() * sizeof(long));
     b.off_like = off;
     off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
+    b.off_slots = off;
+    off += align_up(xs21::thr_stride() * sizeof(xs21::SlotPlan2));
     b.off_delta = off;
     off += align_up(b.cells() * real_size(b.dtype));
     b.off_od = off;
@@ -294,6 +299,12 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
   off += align_up(one);
   L.outs = off;
   off += align_up(8 * 256);
+  // sampler chunk of max_walkers: proposals [5], aux [2], chi^2 [1] per walker,
+  // then P(k) rows [walker][box][max_bins] over every registered box
+  L.samp = off;
+  off += align_up(static_cast<size_t>(max_walkers) * 8 * 8);
+  L.samp_pk = off;
+  off += align_up(static_cast<size_t>(max_walkers) * boxes.size() * xs21::max_bins() * 8);
   L.scratch = off;
   L.scratch_bytes = scratch;
   off += align_up(scratch);
@@ -316,6 +327,7 @@ void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned ch
   c.a_cell = static_cast<T>(wp.a_cell);
   c.chunks = (used + 7) / 8;
   c.partial = wp.partial ? 1 : 0;
+  c.upper = 0;
   std::memcpy(wc_dst, &c, sizeof c);
   const T inf = std::numeric_limits<T>::infinity();
   for (int s = 0; s < xs21::thr_stride(); ++s)
@@ -353,6 +365,7 @@ void put_const(unsigned char* dst, double a_cell, int used, bool partial) {
   c.a_cell = static_cast<T>(a_cell);
   c.chunks = (used + 7) / 8;
   c.partial = partial ? 1 : 0;
+  c.upper = 0;   // set by the planning pass
   std::memcpy(dst, &c, sizeof c);
 }
 
@@ -524,7 +537,9 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const double tb = c->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
   // radii_used: sum over the group's walkers of the radii each filters at
-  const double ion_ops = cells * (radii_used + count * (2.5 * std::log2(static_cast<double>(n)) + 6.0));
+  // (negative when the walkers live on the device: operations not counted)
+  const double ion_ops =
+      radii_used < 0 ? 0.0 : cells * (radii_used + count * (2.5 * std::log2(static_cast<double>(n)) + 6.0));
   return timed(
       c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
       [&] {
@@ -770,6 +785,13 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_counts, b.counts.data(), b.nbins * 8, hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_cut, b.cut.data(), b.cut.size() * sizeof(long), hipMemcpyHostToDevice,
                                  ctx->stream));
+    {
+      const auto slots = xs21::plan::slots2(ctx->phys, b.z, b.radii);
+      b.bplan = xs21::plan::box_plan(ctx->phys, b.z, b.nr());
+      HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_slots, slots.data(), slots.size() * sizeof(xs21::SlotPlan2),
+                                   hipMemcpyHostToDevice, ctx->stream));
+      HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));   // `slots` is a host temporary
+    }
     const size_t dbytes = b.cells() * real_size(b.dtype);
     if (b.dev_src)
       HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_delta, b.dev_src, dbytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -856,8 +878,9 @@ xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
         thr_w = 2 * stride * rs;
         HIPCHECK(ctx, timed(ctx, st, XS21_K_PLAN, 0.0, [&] {
           return xs21::launch_plan2(b.dtype, reinterpret_cast<const xs21::SlotPlan2*>(base + t.slots), b.nr(),
-                                    reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), cnt, base + t.thr,
-                                    static_cast<int>(stride), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c, st);
+                                    reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), cnt, base + t.wc,
+                                    base + t.thr, static_cast<int>(stride), base + t.zt, xs21::kZetaPitch,
+                                    ctx->phys.delta_c, st);
         }));
       }
       for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
@@ -892,6 +915,167 @@ xs21_status xs21_eval_batch2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const
                              double* pk, double* xhi_mean) {
   if (!walkers) return fail(XS21_EINVAL, "null walkers");
   return eval_batch_impl(ctx, boxes, nb, nullptr, walkers, nw, pk, xhi_mean);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Evaluation of `cnt` (<= max_walkers) walkers whose parameters are device
+// rows par[cnt][d] (d = 3: constant efficiency, d = 5: two populations) on
+// the listed boxes, planned on the device: P(k) rows pk[cnt][nb][nbmax] and
+// chi2[cnt] summed over the boxes (every box needs a mock).
+hipError_t eval_dev(xs21_ctx* ctx, const xs21_box* boxes, int nb, int d, const double* par, int cnt, double* pk,
+                    int nbmax, double* chi2) {
+  const hipStream_t st = ctx->stream;
+  const int stride = xs21::thr_stride();
+  const int cap = ctx->max_walkers;
+  size_t off = 0;
+  for (int i = 0; i < nb; ++i) {
+    const BoxRec& b = ctx->boxes[boxes[i]];
+    const size_t rs = real_size(b.dtype);
+    unsigned char* base = ctx->ws + ctx->lay.tables + off;
+    off += b.table_bytes(cap);
+    const auto* slots = reinterpret_cast<const xs21::SlotPlan2*>(ctx->ws + b.off_slots);
+    unsigned char *wc, *thr, *zt = nullptr;
+    size_t thr_w;
+    hipError_t e;
+    if (d == 3) {
+      wc = base;
+      thr = base + align_up(cap * b.wc_size());
+      thr_w = stride * rs;
+      e = timed(ctx, st, XS21_K_PLAN, 0.0,
+                [&] { return xs21::launch_plan1(b.dtype, par, cnt, b.bplan, slots, wc, thr, stride, st); });
+    } else {
+      const Tab2 t = tab2(b, cap);
+      wc = base + t.wc;
+      thr = base + t.thr;
+      zt = base + t.zt;
+      thr_w = 2 * stride * rs;
+      auto* wp = reinterpret_cast<xs21::WalkerPlan2*>(base + t.wp);
+      e = timed(ctx, st, XS21_K_PLAN, 0.0, [&] {
+        hipError_t r = xs21::launch_walker2(b.dtype, par, cnt, b.bplan, slots, wc, wp, st);
+        if (r != hipSuccess) return r;
+        return xs21::launch_plan2(b.dtype, slots, b.nr(), wp, cnt, wc, thr, stride, zt, xs21::kZetaPitch,
+                                  ctx->phys.delta_c, st);
+      });
+    }
+    if (e != hipSuccess) return e;
+    for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
+      const int g = std::min(ctx->group, cnt - g0);
+      const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, g);
+      e = ion_stage(ctx, st, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc + g0 * b.wc_size(),
+                    thr + static_cast<size_t>(g0) * thr_w,
+                    zt ? zt + static_cast<size_t>(g0) * xs21::kZetaPitch * rs : nullptr, g, -1.0);
+      if (e != hipSuccess) return e;
+      e = mem_stage(ctx, st, b, sl, g, pk + (static_cast<size_t>(g0) * nb + i) * nbmax, static_cast<long>(nb) * nbmax,
+                    nbmax, nullptr, 0);
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int i = 0; i < nb; ++i) {
+    const BoxRec& b = ctx->boxes[boxes[i]];
+    hipError_t e = timed(ctx, st, XS21_K_OTHER, static_cast<double>(cnt) * b.nbins * 16, [&] {
+      return xs21::launch_chi2(pk + static_cast<long>(i) * nbmax, static_cast<long>(nb) * nbmax, cnt,
+                               reinterpret_cast<const double*>(ctx->ws + b.off_like), b.nbins, chi2, i == 0, st);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Checks shared by the sampler entry points; fills spec and nbmax.
+xs21_status sampler_args(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_sampler* s, int nw,
+                         xs21::SamplerSpec* spec, int* nbmax) {
+  if (xs21_status r = check_ctx(ctx)) return r;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (!boxes || nb < 1 || !s || nw < 1) return fail(XS21_EINVAL, "empty or null argument");
+  if (nb > static_cast<int>(ctx->boxes.size())) return fail(XS21_EINVAL, "more listed boxes than registered");
+  *nbmax = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (xs21_status r = check_box(ctx, boxes[i])) return r;
+    if (ctx->boxes[boxes[i]].dtype != ctx->boxes[boxes[0]].dtype)
+      return fail(XS21_EINVAL, "boxes of one batch must share a dtype");
+    if (!ctx->boxes[boxes[i]].mock_set) return fail(XS21_ESTATE, "box %d has no mock (xs21_set_mock)", boxes[i]);
+    for (int k = 0; k < i; ++k)
+      if (boxes[k] == boxes[i]) return fail(XS21_EINVAL, "box %d listed twice", boxes[i]);
+    *nbmax = std::max(*nbmax, ctx->boxes[boxes[i]].nbins);
+  }
+  if (s->dim != 3 && s->dim != 5) return fail(XS21_EINVAL, "dim must be 3 or 5");
+  if (!(std::isfinite(s->a) && s->a > 1.0)) return fail(XS21_EINVAL, "stretch scale a must be > 1");
+  for (int c = 0; c < s->dim; ++c)
+    if (!(std::isfinite(s->lo[c]) && std::isfinite(s->hi[c]) && s->lo[c] < s->hi[c]))
+      return fail(XS21_EINVAL, "prior bounds of parameter %d are not finite with lo < hi", c);
+  // the prior box must lie inside the parameters' valid domain
+  bool ok = s->lo[0] > 0.0 && s->lo[1] > 0.0 && s->hi[2] <= 12.0;   // third coordinate: log10 T
+  if (s->dim == 5)
+    ok = ok && s->hi[0] <= 1e6 && s->lo[2] >= 4.0 && s->hi[2] <= 9.0 && std::fabs(s->lo[3]) <= 10.0 &&
+         std::fabs(s->hi[3]) <= 10.0 && std::fabs(s->lo[4]) <= 10.0 && std::fabs(s->hi[4]) <= 10.0;
+  if (!ok) return fail(XS21_EINVAL, "prior box leaves the parameters' valid domain");
+  std::memset(spec, 0, sizeof *spec);
+  for (int c = 0; c < s->dim; ++c) {
+    spec->lo[c] = s->lo[c];
+    spec->hi[c] = s->hi[c];
+  }
+  spec->a = s->a;
+  spec->d = s->dim;
+  return XS21_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xs21_status xs21_mcmc_lnprob(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_sampler* s, const double* x,
+                             int nw, double* lp) {
+  g_error.clear();
+  xs21::SamplerSpec spec;
+  int nbmax = 0;
+  if (xs21_status r = sampler_args(ctx, boxes, nb, s, nw, &spec, &nbmax)) return r;
+  if (!x || !lp) return fail(XS21_EINVAL, "null argument");
+  double* chi2 = reinterpret_cast<double*>(ctx->ws + ctx->lay.samp) + 7 * static_cast<size_t>(ctx->max_walkers);
+  double* pk = reinterpret_cast<double*>(ctx->ws + ctx->lay.samp_pk);
+  for (int c0 = 0; c0 < nw; c0 += ctx->max_walkers) {
+    const int cnt = std::min(ctx->max_walkers, nw - c0);
+    const double* xc = x + static_cast<size_t>(c0) * spec.d;
+    HIPCHECK(ctx, eval_dev(ctx, boxes, nb, spec.d, xc, cnt, pk, nbmax, chi2));
+    HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0,
+                        [&] { return xs21::launch_lnprob(xc, cnt, spec, chi2, lp + c0, ctx->stream); }));
+  }
+  return XS21_OK;
+}
+
+xs21_status xs21_mcmc_step(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_sampler* s, double* x, double* lp,
+                           int nw, const double* u, int32_t* accepted) {
+  g_error.clear();
+  xs21::SamplerSpec spec;
+  int nbmax = 0;
+  if (xs21_status r = sampler_args(ctx, boxes, nb, s, nw, &spec, &nbmax)) return r;
+  if (!x || !lp || !u) return fail(XS21_EINVAL, "null argument");
+  if (nw < 4 || nw % 2) return fail(XS21_EINVAL, "the ensemble needs an even number >= 4 of walkers");
+  const size_t cap = static_cast<size_t>(ctx->max_walkers);
+  double* prop = reinterpret_cast<double*>(ctx->ws + ctx->lay.samp);
+  double* aux = prop + 5 * cap;
+  double* chi2 = aux + 2 * cap;
+  double* pk = reinterpret_cast<double*>(ctx->ws + ctx->lay.samp_pk);
+  const int half = nw / 2;
+  for (int h = 0; h < 2; ++h) {
+    const double* uh = u + static_cast<size_t>(h) * half * 3;
+    for (int c0 = 0; c0 < half; c0 += ctx->max_walkers) {
+      const int cnt = std::min(ctx->max_walkers, half - c0);
+      const int k0 = h * half + c0;
+      HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
+        return xs21::launch_propose(x, k0, (1 - h) * half, half, cnt, uh + 3 * static_cast<size_t>(c0), spec, prop,
+                                    aux, ctx->stream);
+      }));
+      HIPCHECK(ctx, eval_dev(ctx, boxes, nb, spec.d, prop, cnt, pk, nbmax, chi2));
+      HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
+        return xs21::launch_accept(x, lp, k0, cnt, spec.d, uh + 3 * static_cast<size_t>(c0), prop, aux, chi2,
+                                   accepted, ctx->stream);
+      }));
+    }
+  }
+  return XS21_OK;
 }
 
 xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, const double* radii, int n_radii,
@@ -1011,8 +1195,9 @@ xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* w
   ctx->upload_pending = true;
   HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_PLAN, 0.0, [&] {
     return xs21::launch_plan2(b.dtype, reinterpret_cast<const xs21::SlotPlan2*>(base + t.slots), b.nr(),
-                              reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), 1, base + t.thr,
-                              xs21::thr_stride(), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c, ctx->stream);
+                              reinterpret_cast<const xs21::WalkerPlan2*>(base + t.wp), 1, base + t.wc,
+                              base + t.thr, xs21::thr_stride(), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c,
+                              ctx->stream);
   }));
   const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
   HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {

@@ -90,6 +90,7 @@ struct WalkerConst {
   T a_cell;    // 1 / sqrt(2 (sigma^2(M_min) - sigma^2(R_cell))), valid if partial != 0
   int32_t chunks;   // radius slots tested, in groups of 8 (slots run from the cell radius up)
   int32_t partial;  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged
+  int32_t upper;    // two-population walkers: 1 if some slot's flag interval is bounded above
 };
 
 // Two-population efficiency of eq. (9): radius-slot constants (walker
@@ -101,6 +102,7 @@ struct SlotPlan2 {
   double lam_a;     // quadrature range in ln(S - S_R): from lam_a ...
   double lam_b;     // ... to lam_b = ln(ds_cool)
   double cvar;      // c of sigma^2 = c (ln(1 + y) - y / (1 + y))
+  double radius;    // R (Mpc)
 };
 struct WalkerPlan2 {
   double zeta0, alpha, beta;
@@ -109,6 +111,25 @@ struct WalkerPlan2 {
   int32_t used;     // radius slots the walker filters at (from the cell radius up)
   int32_t pad;
 };
+// Walker-independent scalars of one box for planning on the device from
+// device-resident walker parameters (the ensemble sampler): M_min(T) = m1
+// T^1.5, R(M) = (rfac M)^(1/3), k_c(R) = kcnum / R, sigma^2 = cvar (ln(1 + y) -
+// y / (1 + y)) with y = (k_c / k0)^2.
+struct BoxPlan {
+  double m1, rfac, kcnum, k0, cvar, dc;
+  int32_t nr;       // ladder radii (slots)
+  int32_t pad;
+};
+
+// Uniform prior box and stretch scale of the ensemble sampler; d = 3 for
+// (zeta, R_mfp, T_vir), 5 for (zeta0, R_mfp, T_feed, alpha, beta).
+struct SamplerSpec {
+  double lo[5], hi[5];
+  double a;
+  int32_t d;
+  int32_t pad;
+};
+
 // Effective-efficiency table of the cell radius: entry k holds F / erfc(t) at
 // t = (k h)^2, h = sqrt(t_max) / (kZetaTab - 1); rows are kZetaPitch long.
 constexpr int kZetaTab = 1025;

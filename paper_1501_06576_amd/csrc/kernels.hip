@@ -530,7 +530,8 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
 // loads.  Unflagged cells keep x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)).
 //
 // TWO (the two-population efficiency of Section 4, eq. 9): each slot has an
-// interval, flag iff thr[s] <= delta_R <= thr[NR + s], and unflagged cells
+// interval, flag iff thr[s] <= delta_R <= thr[NR + s] (only the lower end is
+// tested for walkers whose intervals are all open above), and unflagged cells
 // keep x_HI = 1 - zeta_eff(t) erfc(t), t = max(a_cell (delta_c - delta_cell), 0),
 // with zeta_eff read from the walker's cell-radius table zt.
 // ---------------------------------------------------------------------------
@@ -548,24 +549,36 @@ __device__ __forceinline__ T zeta_eff(const T* __restrict__ tab, T t) {
   return (x * x1 * (p3 * x2 - T(3) * p2 * x3) + x2 * x3 * (T(3) * p1 * x - p0 * x1)) * T(1.0 / 6.0);
 }
 
-template <typename T, int NR, bool TWO>
-__device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, const T* zt_w,
-                                      T dc) {
+// OR over the tested radius slots as wave-wide lane masks (one compare per
+// slot into a scalar mask; UP: the two-sided interval test).
+template <typename T, int NR, bool UP>
+__device__ __forceinline__ unsigned long long flag_mask(const T (&d)[NR], int chunks, const T* thr_w) {
   static_assert(NR % 8 == 0, "radius slots come in groups of 8");
-  // OR over radii as wave-wide lane masks: one compare into a scalar mask per slot
   unsigned long long m = 0;
 #pragma unroll
   for (int g = 0; g < NR / 8; ++g) {
-    if (g >= c.chunks) break;
+    if (g >= chunks) break;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int s = 8 * g + k;
-      if constexpr (TWO)
+      if constexpr (UP)
         m |= __ballot((d[s] >= thr_w[s]) & (d[s] <= thr_w[NR + s]));
       else
         m |= __ballot(d[s] >= thr_w[s]);
     }
   }
+  return m;
+}
+
+template <typename T, int NR, bool TWO>
+__device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, const T* zt_w,
+                                      T dc) {
+  // two-population walkers whose intervals are all open above test one end
+  unsigned long long m;
+  if constexpr (TWO)
+    m = c.upper ? flag_mask<T, NR, true>(d, c.chunks, thr_w) : flag_mask<T, NR, false>(d, c.chunks, thr_w);
+  else
+    m = flag_mask<T, NR, false>(d, c.chunks, thr_w);
   const bool flag = (m >> __lane_id()) & 1ull;
   T x = T(1);
   if (flag) {

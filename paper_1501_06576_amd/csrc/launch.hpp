@@ -67,12 +67,30 @@ hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, con
                               void* dtb, hipStream_t s);
 // Two-population planning (Section 4, eq. 9) of nw walkers on one box:
 // slots[nr] (device, slot 0 = cell radius), wp[nw] (device) -> thresholds
-// thr[w][2][stride] (lo, hi; +inf where unused) and the cell-radius
+// thr[w][2][stride] (lo, hi; +inf where unused), wc[w].upper set where some
+// hi is finite (wc[w].upper must be 0 before), and the cell-radius
 // effective-efficiency tables zt[w][pitch], in `dtype`.
 struct SlotPlan2;
 struct WalkerPlan2;
-hipError_t launch_plan2(int dtype, const SlotPlan2* slots, int nr, const WalkerPlan2* wp, int nw, void* thr,
-                        int stride, void* zt, int pitch, double dc, hipStream_t s);
+hipError_t launch_plan2(int dtype, const SlotPlan2* slots, int nr, const WalkerPlan2* wp, int nw, void* wc,
+                        void* thr, int stride, void* zt, int pitch, double dc, hipStream_t s);
+// Planning from device walker parameters (the sampler): constant-efficiency
+// rows par[nw][3] -> walker constants wc[nw] and thresholds thr[nw][stride];
+// two-population rows par[nw][5] -> wc[nw] and the inputs wp[nw] of launch_plan2.
+struct BoxPlan;
+struct SamplerSpec;
+hipError_t launch_plan1(int dtype, const double* par, int nw, const BoxPlan& b, const SlotPlan2* slots, void* wc,
+                        void* thr, int stride, hipStream_t s);
+hipError_t launch_walker2(int dtype, const double* par, int nw, const BoxPlan& b, const SlotPlan2* slots, void* wc,
+                          WalkerPlan2* wp, hipStream_t s);
+// Stretch-move proposals of walkers k0 .. k0 + count - 1 (partners among the
+// `half` walkers from o0), their acceptance given chi^2, and ln p of walkers.
+hipError_t launch_propose(const double* x, int k0, int o0, int half, int count, const double* u,
+                          const SamplerSpec& spec, double* prop, double* aux, hipStream_t s);
+hipError_t launch_accept(double* x, double* lp, int k0, int count, int d, const double* u, const double* prop,
+                         const double* aux, const double* chi2, int32_t* accepted, hipStream_t s);
+hipError_t launch_lnprob(const double* x, int count, const SamplerSpec& spec, const double* chi2, double* lp,
+                         hipStream_t s);
 // Deterministic reduction of the bin and x_HI partial sums, one walker per block.
 hipError_t launch_finalize(int nwalkers, const double* part, long ntiles, int nbins, const double* xpart, long nblk,
                            const double* counts, double pscale, double inv_cells, double* pk, long pk_stride,

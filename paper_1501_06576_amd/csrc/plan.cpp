@@ -160,8 +160,22 @@ std::vector<SlotPlan2> slots2(const xs21_physics& p, double z, const std::vector
     o.lam_a = std::log(o.s_r) - 32.0;
     o.lam_b = o.ds_cool > 0.0 ? std::log(o.ds_cool) : o.lam_a;
     o.cvar = cvar;
+    o.radius = r;
   }
   return out;
+}
+
+BoxPlan box_plan(const xs21_physics& p, double z, int nr) {
+  BoxPlan b{};
+  b.m1 = min_mass(p, 1.0, z);
+  b.rfac = 3.0 / (4.0 * kPi * p.omega_m * kRhoCritH2 * p.h * p.h);
+  b.kcnum = std::cbrt(4.5 * kPi);
+  b.k0 = p.pk_k0;
+  const double d = (1.0 + p.z_ref) / (1.0 + z);
+  b.cvar = d * d * p.pk_amp * std::pow(p.pk_k0, 4) / (4.0 * kPi * kPi);
+  b.dc = p.delta_c;
+  b.nr = nr;
+  return b;
 }
 
 WalkerPlan2 walker2(const xs21_physics& p, double z, const xs21_walker2& w, int used) {

@@ -61,6 +61,8 @@ std::vector<double> twiddles(int ntab);
 // radius), and one walker's inputs of the device planning pass.
 std::vector<SlotPlan2> slots2(const xs21_physics& p, double z, const std::vector<double>& radii);
 WalkerPlan2 walker2(const xs21_physics& p, double z, const xs21_walker2& w, int used);
+// Scalars of a box for planning on the device (BoxPlan).
+BoxPlan box_plan(const xs21_physics& p, double z, int nr);
 
 bool valid_physics(const xs21_physics& p);
 bool valid_walker(const xs21_walker& w);

@@ -174,11 +174,12 @@ __device__ double root_f1(double a, double Fa, double b, double Fb, const double
 // One wave per (radius slot, walker): thresholds thr[w][0][s] = lo and
 // thr[w][1][s] = hi (stride slots each) with F >= 1 exactly for lo <= delta_R
 // <= hi; both +inf where no cell can be flagged (unused slot, sphere lighter
-// than M_cool, or F < 1 everywhere).
+// than M_cool, or F < 1 everywhere).  A finite hi sets the walker's `upper`
+// (which starts at 0).
 template <typename T>
 __global__ __launch_bounds__(64) void k_plan2_thr(const SlotPlan2* __restrict__ slots, int nr,
-                                                  const WalkerPlan2* __restrict__ wp, T* __restrict__ thr,
-                                                  int stride, double dc) {
+                                                  const WalkerPlan2* __restrict__ wp, WalkerConst<T>* __restrict__ wc,
+                                                  T* __restrict__ thr, int stride, double dc) {
   __shared__ double C[kNodesMax];
   __shared__ double E[kNodesMax];
   __shared__ double fs[64];
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(64) void k_plan2_thr(const SlotPlan2* __restrict__ 
   if (lane == 0) {
     lo[s] = static_cast<T>(dlo);
     hi[s] = static_cast<T>(dhi);
+    if (static_cast<T>(dhi) < inf) atomicOr(&wc[w].upper, 1);   // the walker needs two-sided tests
   }
 }
 
@@ -273,18 +275,20 @@ __global__ __launch_bounds__(256) void k_plan2_tab(const SlotPlan2* __restrict__
 
 }  // namespace
 
-hipError_t launch_plan2(int dtype, const SlotPlan2* slots, int nr, const WalkerPlan2* wp, int nw, void* thr,
-                        int stride, void* zt, int pitch, double dc, hipStream_t s) {
+hipError_t launch_plan2(int dtype, const SlotPlan2* slots, int nr, const WalkerPlan2* wp, int nw, void* wc,
+                        void* thr, int stride, void* zt, int pitch, double dc, hipStream_t s) {
   if (nr < 1 || nr > stride || nw < 1 || pitch < kZetaTab) return hipErrorInvalidValue;
   const unsigned tab_blocks = static_cast<unsigned>((pitch + 255) / 256);
   if (dtype == kF64) {
     hipLaunchKernelGGL(k_plan2_thr<double>, dim3(static_cast<unsigned>(stride), static_cast<unsigned>(nw)), dim3(64),
-                       0, s, slots, nr, wp, static_cast<double*>(thr), stride, dc);
+                       0, s, slots, nr, wp, static_cast<WalkerConst<double>*>(wc), static_cast<double*>(thr), stride,
+                       dc);
     hipLaunchKernelGGL(k_plan2_tab<double>, dim3(tab_blocks, static_cast<unsigned>(nw)), dim3(256), 0, s, slots, wp,
                        static_cast<double*>(zt), pitch);
   } else {
     hipLaunchKernelGGL(k_plan2_thr<float>, dim3(static_cast<unsigned>(stride), static_cast<unsigned>(nw)), dim3(64),
-                       0, s, slots, nr, wp, static_cast<float*>(thr), stride, dc);
+                       0, s, slots, nr, wp, static_cast<WalkerConst<float>*>(wc), static_cast<float*>(thr), stride,
+                       dc);
     hipLaunchKernelGGL(k_plan2_tab<float>, dim3(tab_blocks, static_cast<unsigned>(nw)), dim3(256), 0, s, slots, wp,
                        static_cast<float*>(zt), pitch);
   }

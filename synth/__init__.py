@@ -121,6 +121,11 @@ def draw_walkers2(count: int, seed: int) -> np.ndarray:
     return out
 
 
+def uniforms(shape, seed: int) -> np.ndarray:
+    """float64 uniforms in [0, 1) of the given shape (the sampler's random inputs)."""
+    return np.random.Generator(np.random.PCG64(seed)).random(shape)
+
+
 @dataclasses.dataclass(frozen=True)
 class BoxSpec:
     n: int

@@ -18,6 +18,8 @@
 //   materialize <box> <walker> -> mat_b{b}_w{w}_{xhi,dtb}.bin
 //   batch2 <nbmax> [tag]       -> batch2<tag>_{pk,xhi}.bin for the walker2 list
 //   materialize2 <box> <walker2> -> mat2_b{b}_w{w}_{xhi,dtb}.bin
+//   mcmc <dim> <a> <nw> <steps> <lo/hi file> <x file> <u file> <tag>
+//        -> mcmc<tag>_x.bin [steps+1][nw][dim], _lp.bin [steps+1][nw], _acc.bin [steps][nw] int32
 //   smoothed <box> <index>     -> sm_b{b}_j{j}.bin
 //   pk <box> <field file>      -> fpk_b{b}.bin
 #include <cstdio>
@@ -128,6 +130,45 @@ int main(int argc, char** argv) {
       std::snprintf(pre, sizeof pre, "%s/mat2_b%d_w%d_", out.c_str(), b, w);
       write_file(std::string(pre) + "xhi.bin", xhi.data(), xhi.size());
       write_file(std::string(pre) + "dtb.bin", dtb.data(), dtb.size());
+    } else if (cmd == "mcmc") {
+      int dim, nw, steps;
+      double a;
+      std::string bf, xf, uf, tag;
+      is >> dim >> a >> nw >> steps >> bf >> xf >> uf >> tag;
+      xs21_sampler sp{};
+      sp.dim = dim;
+      sp.a = a;
+      auto bounds = read_file(bf);
+      for (int c = 0; c < dim; ++c) {
+        sp.lo[c] = reinterpret_cast<const double*>(bounds.data())[c];
+        sp.hi[c] = reinterpret_cast<const double*>(bounds.data())[dim + c];
+      }
+      auto xv = read_file(xf);
+      auto uv = read_file(uf);
+      std::vector<double> x(reinterpret_cast<const double*>(xv.data()),
+                            reinterpret_cast<const double*>(xv.data()) + static_cast<size_t>(nw) * dim);
+      std::vector<double> lp(nw);
+      std::vector<int32_t> acc(nw);
+      std::vector<double> xs, lps;
+      std::vector<int32_t> accs;
+      const int nb = static_cast<int>(box_n.size());
+      std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
+      CHECK(xs21_mcmc_lnprob(ctx, bx.data(), nb, &sp, x.data(), nw, lp.data()));
+      CHECK(xs21_sync(ctx));
+      xs.insert(xs.end(), x.begin(), x.end());
+      lps.insert(lps.end(), lp.begin(), lp.end());
+      for (int t = 0; t < steps; ++t) {
+        const double* u = reinterpret_cast<const double*>(uv.data()) + static_cast<size_t>(t) * nw * 3;
+        CHECK(xs21_mcmc_step(ctx, bx.data(), nb, &sp, x.data(), lp.data(), nw, u, acc.data()));
+        CHECK(xs21_sync(ctx));
+        xs.insert(xs.end(), x.begin(), x.end());
+        lps.insert(lps.end(), lp.begin(), lp.end());
+        accs.insert(accs.end(), acc.begin(), acc.end());
+      }
+      write_file(out + "/mcmc" + tag + "_x.bin", xs.data(), xs.size() * 8);
+      write_file(out + "/mcmc" + tag + "_lp.bin", lps.data(), lps.size() * 8);
+      write_file(out + "/mcmc" + tag + "_acc.bin", accs.data(), accs.size() * 4);
     } else if (cmd == "box") {
       if (!ctx) CHECK(xs21_create(&ctx, 0, nullptr, &phys));
       std::string file, dt;

@@ -107,6 +107,26 @@ inline int __float_as_int(float f) { return __builtin_bit_cast(int, f); }
 inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
 inline float __fdividef(float a, float b) { return a / b; }
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
+inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
+// Device math function without a host counterpart: the inverse of erfc on
+// (0, 2), by bisection on std::erfc (strictly decreasing) and Newton polish.
+inline double erfcinv(double y) {
+  if (!(y > 0.0 && y < 2.0)) return y == 0.0 ? HUGE_VAL : (y == 2.0 ? -HUGE_VAL : NAN);
+  double lo = -30.0, hi = 30.0;
+  for (int i = 0; i < 200; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (std::erfc(mid) > y) lo = mid; else hi = mid;
+  }
+  double x = 0.5 * (lo + hi);
+  for (int i = 0; i < 3; ++i) {
+    const double df = -1.1283791670955126 * std::exp(-x * x);
+    if (df == 0.0) break;
+    const double nx = x - (std::erfc(x) - y) / df;
+    if (!(nx >= lo - 1e-12 && nx <= hi + 1e-12)) break;
+    x = nx;
+  }
+  return x;
+}
 template <typename V>
 inline void __builtin_nontemporal_store(V v, V* p) { *p = v; }
 template <typename V>

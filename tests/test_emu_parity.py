@@ -267,3 +267,75 @@ def test_emu_two_population():
             same = (x == 0) == ev.flagged
             assert np.mean(~same) == 0.0
             assert np.abs(x - ev.x_hi)[same].max() <= 2e-7
+
+
+def _oracle_chain(boxes, specs, mocks, dim, lo, hi, x0, u, a=2.0):
+    """The oracle sampler's chain with ln p = -chi^2 / 2 from full oracle evaluations."""
+    def loglike(p):
+        tot = 0.0
+        for bi, (n, box, z, nb) in enumerate(specs):
+            radii = oracle.walker_radii(oracle.shared_radii(n, box, PHYS), p[1])
+            if dim == 3:
+                ev = oracle.evaluate(boxes[bi], box, z, (p[0], p[1], 10 ** p[2]), radii, nb, PHYS)
+            else:
+                ev = oracle.two_population.evaluate(boxes[bi], box, z, (p[0], p[1], 10 ** p[2], p[3], p[4]),
+                                                    radii, nb, PHYS)
+            tot += oracle.likelihood.chi2(ev.delta2, mocks[bi], np.zeros(nb), ev.k_mean, ev.counts)
+        return -0.5 * tot
+    lp_fn = oracle.sampler.box_prior(lo, hi, loglike)
+    x = x0.copy()
+    lp = np.array([lp_fn(v) for v in x])
+    xs, lps, accs = [x.copy()], [lp.copy()], []
+    for t in range(u.shape[0]):
+        accs.append(oracle.sampler.step(x, lp, u[t], lp_fn, a))
+        xs.append(x.copy())
+        lps.append(lp.copy())
+    return np.array(xs), np.array(lps), np.array(accs)
+
+
+@pytest.mark.parametrize("dim", [3, 5])
+def test_emu_mcmc_chain(dim):
+    # steps of a small ensemble in walker chunks of 2 (a half of 3 walkers is
+    # ragged), against the oracle sampler fed with the same uniforms
+    if dim == 3:
+        specs = [(16, 32.0, 9.0, 5)]
+        lo, hi = [5.0, 5.0, 4.0], [100.0, 20.0, 5.3]
+        fid = (30.0, 15.0, np.log10(5e4))
+        nw, steps = 6, 2
+    else:
+        specs = [(8, 24.0, 8.0, 3)]
+        lo, hi = [5.0, 5.0, 4.0, -4 / 3, -4 / 3], [100.0, 20.0, 5.3, 10 / 3, 10 / 3]
+        fid = (70.0, 15.0, 4.7, 4 / 3, -1 / 3)
+        nw, steps = 4, 1
+    rng_x = synth.uniforms((nw, dim), 200 + dim)
+    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * (0.25 + 0.5 * rng_x)   # inside the prior
+    u = synth.uniforms((steps, 2, nw // 2, 3), 300 + dim)
+    run = eh.EmuRun(storage="f64", max_walkers=2, phys={"pk_amp": AMP})
+    boxes, mocks = [], []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=90 + i, amp=AMP, dtype=np.float64)
+        boxes.append(d)
+        run.box(d, box, z, nb)
+        radii = oracle.walker_radii(oracle.shared_radii(n, box, PHYS), fid[1])
+        if dim == 3:
+            ev = oracle.evaluate(d, box, z, (fid[0], fid[1], 10 ** fid[2]), radii, nb, PHYS)
+        else:
+            ev = oracle.two_population.evaluate(d, box, z, (fid[0], fid[1], 10 ** fid[2], fid[3], fid[4]), radii,
+                                                nb, PHYS)
+        mocks.append(ev.delta2)
+    run.cmd("prepare")
+    for i in range(len(specs)):
+        run.cmd(f"mock {i} {run.write_array(f'mock{i}.bin', mocks[i])} - 0.25 0.15 1.0")
+    bpath = run.write_array("bounds.bin", np.concatenate([lo, hi]).astype(np.float64))
+    xpath = run.write_array("x0.bin", x0.astype(np.float64))
+    upath = run.write_array("u.bin", u.astype(np.float64))
+    run.cmd(f"mcmc {dim} 2.0 {nw} {steps} {bpath} {xpath} {upath} A")
+    run.run()
+    gx = run.read("mcmcA_x.bin", np.float64, (steps + 1, nw, dim))
+    glp = run.read("mcmcA_lp.bin", np.float64, (steps + 1, nw))
+    gacc = run.read("mcmcA_acc.bin", np.int32, (steps, nw))
+    ox, olp, oacc = _oracle_chain(boxes, specs, mocks, dim, lo, hi, x0, u)
+    np.testing.assert_array_equal(gacc.astype(bool), oacc)
+    np.testing.assert_allclose(gx, ox, rtol=1e-12)
+    tol = 1e-9 if dim == 3 else 1e-5
+    np.testing.assert_allclose(glp, olp, rtol=tol)

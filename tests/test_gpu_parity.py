@@ -504,3 +504,148 @@ def test_two_population_256_sampled(xs):
         np.testing.assert_allclose(pk[i, 1], p_ref, rtol=2e-4)
         assert abs(xhi[i, 1] - float(np.mean(x, dtype=np.float64))) <= 1e-5
     ctx.close()
+
+
+# ------------------------------------------------------------------ ensemble sampler (Section 2.3)
+
+def _oracle_chain(box_data, specs, mocks, dim, lo, hi, x0, u):
+    def loglike(p):
+        tot = 0.0
+        for d, (n, box, z, nb), mock in zip(box_data, specs, mocks):
+            radii = oracle.walker_radii(oracle.shared_radii(n, box, PHYS), p[1])
+            if dim == 3:
+                ev = oracle.evaluate(d, box, z, (p[0], p[1], 10 ** p[2]), radii, nb, PHYS)
+            else:
+                ev = oracle.two_population.evaluate(d, box, z, (p[0], p[1], 10 ** p[2], p[3], p[4]), radii, nb,
+                                                    PHYS)
+            tot += oracle.likelihood.chi2(ev.delta2, mock, np.zeros(nb), ev.k_mean, ev.counts)
+        return -0.5 * tot
+    lp_fn = oracle.sampler.box_prior(lo, hi, loglike)
+    x = x0.copy()
+    lp = np.array([lp_fn(v) for v in x])
+    xs, lps, accs = [x.copy()], [lp.copy()], []
+    for t in range(u.shape[0]):
+        accs.append(oracle.sampler.step(x, lp, u[t], lp_fn))
+        xs.append(x.copy())
+        lps.append(lp.copy())
+    return np.array(xs), np.array(lps), np.array(accs)
+
+
+PRIOR3 = ([5.0, 5.0, 4.0], [100.0, 20.0, 5.3])
+PRIOR5 = ([5.0, 5.0, 4.0, -4 / 3, -4 / 3], [100.0, 20.0, 5.3, 10 / 3, 10 / 3])
+
+
+@pytest.mark.parametrize("dim", [3, 5])
+def test_mcmc_chain_vs_oracle(xs, dim):
+    """FP64: a few ensemble steps through the C-ABI against the oracle sampler with the
+    same uniforms (walker chunks of 3, ragged halves): identical moves, same chain."""
+    import torch
+    if dim == 3:
+        specs = [(32, 64.0, 9.0, 6), (16, 32.0, 8.0, 4)]
+        fid, nw, steps = (30.0, 15.0, np.log10(5e4)), 8, 3
+        lo, hi = PRIOR3
+    else:
+        specs = [(16, 32.0, 8.5, 4)]
+        fid, nw, steps = (70.0, 15.0, 4.7, 4 / 3, -1 / 3), 6, 2
+        lo, hi = PRIOR5
+    ctx = _ctx(xs)
+    data, mocks, hs = [], [], []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=95 + i, amp=AMP, dtype=np.float64)
+        data.append(d)
+        hs.append(ctx.add_box(d, box, z, nb))
+    ctx.prepare("f64", max_walkers=3, max_plain_radii=30)
+    for h, d, (n, box, z, nb) in zip(hs, data, specs):
+        radii = oracle.walker_radii(oracle.shared_radii(n, box, PHYS), fid[1])
+        if dim == 3:
+            ev = oracle.evaluate(d, box, z, (fid[0], fid[1], 10 ** fid[2]), radii, nb, PHYS)
+        else:
+            ev = oracle.two_population.evaluate(d, box, z, (fid[0], fid[1], 10 ** fid[2], fid[3], fid[4]), radii, nb,
+                                                PHYS)
+        mocks.append(ev.delta2)
+        ctx.set_mock(h, ev.delta2)
+    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * (0.25 + 0.5 * synth.uniforms((nw, dim), 210 + dim))
+    u = synth.uniforms((steps, 2, nw // 2, 3), 310 + dim)
+    spec = xs.sampler(lo, hi)
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    lp = ctx.mcmc_lnprob(hs, spec, x)
+    acc = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    gx, glp, gacc = [x.cpu().numpy().copy()], [lp.cpu().numpy().copy()], []
+    for t in range(steps):
+        ctx.mcmc_step(hs, spec, x, lp, torch.tensor(u[t], dtype=torch.float64, device="cuda"), acc)
+        gx.append(x.cpu().numpy().copy())
+        glp.append(lp.cpu().numpy().copy())
+        gacc.append(acc.cpu().numpy().astype(bool))
+    ox, olp, oacc = _oracle_chain(data, specs, mocks, dim, lo, hi, x0, u)
+    print(f"[mcmc dim={dim}] accepted {int(np.sum(gacc))}/{nw * steps}; max |dlp| = "
+          f"{np.max(np.abs(np.array(glp) - olp)):.2e}", flush=True)
+    np.testing.assert_array_equal(np.array(gacc), oacc)
+    np.testing.assert_allclose(np.array(gx), ox, rtol=1e-12)
+    np.testing.assert_allclose(np.array(glp), olp, rtol=1e-9 if dim == 3 else 1e-5)
+    ctx.close()
+
+
+def test_mcmc_256_consistency(xs):
+    """The benchmark geometry (256^3 x 3 z, FP32), 128 walkers: device-planned ln p equals
+    -chi^2/2 of the host-planned batch; after steps, walkers that did not move keep x and
+    ln p, and every ln p equals a fresh evaluation of its walker."""
+    import torch
+    wl = synth.WORKLOADS["batched-256"]
+    boxes = synth.workload_boxes(wl, AMP)
+    ctx = _ctx(xs)
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    ctx.prepare("f32", max_walkers=64, max_plain_radii=40)
+    fid = (30.0, 15.0, 5e4)
+    fpk, _ = ctx.eval_batch(hs, [fid])
+    fpk = fpk.cpu().numpy()
+    for i, h in enumerate(hs):
+        km, _ = ctx.bins(h)
+        ctx.set_mock(h, km ** 3 * fpk[0, i, :len(km)] / (2 * np.pi ** 2))
+    lo, hi = PRIOR3
+    nw = 128
+    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * synth.uniforms((nw, 3), 220)
+    spec = xs.sampler(lo, hi)
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    lp = ctx.mcmc_lnprob(hs, spec, x)
+    walkers = np.column_stack([x0[:, 0], x0[:, 1], 10 ** x0[:, 2]])
+    pk, _ = ctx.eval_batch(hs, walkers)
+    ref = -0.5 * ctx.chi2(hs, pk).cpu().numpy()
+    np.testing.assert_allclose(lp.cpu().numpy(), ref, rtol=1e-4)
+    acc = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    for t in range(2):
+        xb, lpb = x.clone(), lp.clone()
+        ctx.mcmc_step(hs, spec, x, lp, torch.tensor(synth.uniforms((2, nw // 2, 3), 320 + t), device="cuda"), acc)
+        moved = acc.cpu().numpy().astype(bool)
+        assert 0 < moved.sum() < nw
+        np.testing.assert_array_equal(x.cpu().numpy()[~moved], xb.cpu().numpy()[~moved])
+        np.testing.assert_array_equal(lp.cpu().numpy()[~moved], lpb.cpu().numpy()[~moved])
+        assert np.all(np.any(x.cpu().numpy()[moved] != xb.cpu().numpy()[moved], axis=1))
+    xn = x.cpu().numpy()
+    assert np.all((xn >= np.asarray(lo)) & (xn <= np.asarray(hi)))
+    np.testing.assert_allclose(ctx.mcmc_lnprob(hs, spec, x).cpu().numpy(), lp.cpu().numpy(), rtol=1e-9)
+    ctx.close()
+
+
+def test_mcmc_rejects_bad_arguments(xs):
+    import torch
+    ctx = _ctx(xs)
+    d = synth.make_box(16, 32.0, 9.0, seed=3, amp=AMP, dtype=np.float32)
+    h = ctx.add_box(d, 32.0, 9.0, 4)
+    ctx.prepare("f32", max_walkers=4, max_plain_radii=30)
+    x = torch.tensor([[30.0, 10.0, 4.5]] * 4, dtype=torch.float64, device="cuda")
+    lp = torch.zeros(4, dtype=torch.float64, device="cuda")
+    u = torch.full((2, 2, 3), 0.5, dtype=torch.float64, device="cuda")
+    with pytest.raises(xs.Xs21Error):
+        ctx.mcmc_lnprob([h], xs.sampler(*PRIOR3), x)            # no mock yet
+    ctx.set_mock(h, np.ones(4))
+    with pytest.raises(xs.Xs21Error):
+        ctx.mcmc_lnprob([h], xs.sampler([0.0, 5.0, 4.0], [100.0, 20.0, 5.3]), x)   # zeta >= 0 allowed in prior
+    with pytest.raises(xs.Xs21Error):
+        ctx.mcmc_step([h], xs.sampler(*PRIOR3), x[:3], lp[:3], u)   # odd ensemble
+    with pytest.raises(xs.Xs21Error):
+        ctx.mcmc_step([h], xs.sampler(*PRIOR3, a=1.0), x, lp, u)
+    lp = ctx.mcmc_lnprob([h], xs.sampler(*PRIOR3), x)
+    assert np.isfinite(lp.cpu().numpy()).all()
+    out = ctx.mcmc_lnprob([h], xs.sampler([5.0, 5.0, 4.6], [100.0, 20.0, 5.3]), x)   # walkers below the prior
+    assert np.all(np.isneginf(out.cpu().numpy()))
+    ctx.close()
