@@ -302,12 +302,21 @@ class Context:
                                    _dptr(pk), _dptr(km), _dptr(cn), ctypes.byref(xm)))
         return {"x_hi": x_hi, "dtb": dtb, "pk": pk, "k_mean": km, "counts": cn, "xhi_mean": xm.value}
 
+    def _dev(self, t, shape, dtype, name):
+        """The C-ABI cannot check device buffer sizes: check dtype, device, layout and shape here."""
+        if (t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape)):
+            raise ValueError(f"{name}: need a contiguous {dtype} device tensor of shape {tuple(shape)}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
     def mcmc_lnprob(self, boxes: Sequence[int], spec: Sampler, x, lp=None):
         """ln p (-chi^2/2 in the prior, -inf outside) of walkers x (device float64 [nw, dim])."""
         bx = (ctypes.c_int32 * len(boxes))(*boxes)
         nw = int(x.shape[0])
+        f64 = self.torch.float64
+        self._dev(x, (nw, spec.dim), f64, "x")
         if lp is None:
-            lp = self.torch.empty(nw, dtype=self.torch.float64, device=self.device)
+            lp = self.torch.empty(nw, dtype=f64, device=self.device)
+        self._dev(lp, (nw,), f64, "lp")
         _check(library().xs21_mcmc_lnprob(self._ctx, bx, len(boxes), ctypes.byref(spec),
                                           ctypes.c_void_p(x.data_ptr()), nw, ctypes.c_void_p(lp.data_ptr())))
         return lp
@@ -316,6 +325,13 @@ class Context:
         """One stretch-move ensemble step in place on x / lp (device float64); u: device float64
         [2, nw/2, 3] uniforms; accepted: optional device int32 [nw]."""
         bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        nw = int(x.shape[0])
+        f64 = self.torch.float64
+        self._dev(x, (nw, spec.dim), f64, "x")
+        self._dev(lp, (nw,), f64, "lp")
+        self._dev(u, (2, nw // 2, 3), f64, "u")
+        if accepted is not None:
+            self._dev(accepted, (nw,), self.torch.int32, "accepted")
         acc = ctypes.c_void_p(accepted.data_ptr()) if accepted is not None else None
         _check(library().xs21_mcmc_step(self._ctx, bx, len(boxes), ctypes.byref(spec), ctypes.c_void_p(x.data_ptr()),
                                         ctypes.c_void_p(lp.data_ptr()), int(x.shape[0]),

@@ -641,7 +641,9 @@ def test_mcmc_rejects_bad_arguments(xs):
     with pytest.raises(xs.Xs21Error):
         ctx.mcmc_lnprob([h], xs.sampler([0.0, 5.0, 4.0], [100.0, 20.0, 5.3]), x)   # zeta >= 0 allowed in prior
     with pytest.raises(xs.Xs21Error):
-        ctx.mcmc_step([h], xs.sampler(*PRIOR3), x[:3], lp[:3], u)   # odd ensemble
+        ctx.mcmc_step([h], xs.sampler(*PRIOR3), x[:3], lp[:3], u[:, :1].contiguous())   # odd ensemble
+    with pytest.raises(ValueError):
+        ctx.mcmc_step([h], xs.sampler(*PRIOR3), x, lp, u[:, :1].contiguous())   # uniforms of the wrong shape
     with pytest.raises(xs.Xs21Error):
         ctx.mcmc_step([h], xs.sampler(*PRIOR3, a=1.0), x, lp, u)
     lp = ctx.mcmc_lnprob([h], xs.sampler(*PRIOR3), x)
