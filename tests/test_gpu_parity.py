@@ -651,3 +651,28 @@ def test_mcmc_rejects_bad_arguments(xs):
     out = ctx.mcmc_lnprob([h], xs.sampler([5.0, 5.0, 4.6], [100.0, 20.0, 5.3]), x)   # walkers below the prior
     assert np.all(np.isneginf(out.cpu().numpy()))
     ctx.close()
+
+
+def test_two_population_bf16_storage_with_velocity(xs):
+    """Two-population walkers on BF16-stored smoothed boxes with the velocity-gradient factor
+    of eq. (4) switched on (32^3, 64 Mpc, z = 9): reported against the oracle, loose bounds
+    as for BF16 storage with constant efficiency."""
+    n, box, z, nb = 32, 64.0, 9.0, 6
+    d = synth.make_box(n, box, z, seed=47, amp=AMP, dtype=np.float32)
+    phys = oracle.Physics(pk_amp=AMP, velocity=True, dvdr_max=0.2)
+    ctx = _ctx(xs, velocity=1, dvdr_max=0.2)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("bf16", max_walkers=4, max_plain_radii=30)
+    walkers = EDGE2[:4]
+    pk, xhi = ctx.eval_batch2([b], walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    shared = ctx.radii(b)
+    for i, w in enumerate(walkers):
+        ev = oracle.two_population.evaluate(d.astype(np.float64), box, z, w, oracle.walker_radii(shared, w[1]), nb,
+                                            phys)
+        x, _ = ctx.materialize2(b, w)
+        flips, rel = report(f"two-pop-bf16-vel w{i}", x.cpu().numpy(), ev, pk[i, 0], xhi[i, 0])
+        assert flips <= 3e-2 and rel <= 5e-2
+        assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-2
+    ctx.close()
