@@ -554,6 +554,9 @@ __device__ __forceinline__ T zeta_eff(const T* __restrict__ tab, T t) {
 template <typename T, int NR, bool UP>
 __device__ __forceinline__ unsigned long long flag_mask(const T (&d)[NR], int chunks, const T* thr_w) {
   static_assert(NR % 8 == 0, "radius slots come in groups of 8");
+  // the cell radius is always tested, so the first group's thresholds load
+  // together with the walker constants (one scalar-load wait fewer per walker)
+  __builtin_assume(chunks >= 1);
   unsigned long long m = 0;
 #pragma unroll
   for (int g = 0; g < NR / 8; ++g) {

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -108,6 +109,11 @@ inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
 inline float __fdividef(float a, float b) { return a / b; }
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
 inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
+// Clang's optimiser hint; here it is checked instead
+#define __builtin_assume(cond) \
+  do {                         \
+    if (!(cond)) std::abort(); \
+  } while (0)
 // Device math function without a host counterpart: the inverse of erfc on
 // (0, 2), by bisection on std::erfc (strictly decreasing) and Newton polish.
 inline double erfcinv(double y) {
