@@ -582,7 +582,8 @@ __device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c,
     m = c.upper ? flag_mask<T, NR, true>(d, c.chunks, thr_w) : flag_mask<T, NR, false>(d, c.chunks, thr_w);
   else
     m = flag_mask<T, NR, false>(d, c.chunks, thr_w);
-  const bool flag = (m >> __lane_id()) & 1ull;
+  // this lane's bit of the wave mask, as a lane predicate (no per-lane shift)
+  const bool flag = __builtin_amdgcn_inverse_ballot_w64(m);
   T x = T(1);
   if (flag) {
     x = T(0);
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        const T xh = cell_xhi<T, kNrMax, TWO>(d, wc[w], thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
+        const T xh = cell_xhi<T, kNrMax, TWO>(d, load_walker(wc + w), thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
                                               zt + static_cast<size_t>(w) * kZetaPitch, dc);
         ldsr[2 * (q * N + x) + row] = tb * xh * od;
         if constexpr (IS::NT >= 64) {

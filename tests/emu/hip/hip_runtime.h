@@ -95,6 +95,7 @@ inline unsigned long long __ballot(int pred) {
   return ::hipemu::wave_ballot(pred != 0);
 }
 inline unsigned __lane_id() { return static_cast<unsigned>(::hipemu::lane_id()); }
+inline bool __builtin_amdgcn_inverse_ballot_w64(unsigned long long m) { return (m >> __lane_id()) & 1ull; }
 
 inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
   return ::hipemu::wave_dpp(old, src, ctrl, row_mask, bank_mask, bound_ctrl);
