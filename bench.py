@@ -271,6 +271,23 @@ def main():
                           "vs_steady_eval": round((ne / (ms_m * 1e-3)) / (nw / (ms_steady * 1e-3)), 4),
                           "kernel_ms_per_step": {k: round(v["ms"], 4) for k, v in prof_m.items() if v["launches"]},
                           "note": "stretch move (a = 2) over (zeta, R_mfp, log10 T_vir) in [5,100]x[5,20]x[4,5.3]"}
+        # the same loop over two-population walkers (zeta0, R_mfp, log10 T_feed, alpha, beta)
+        lo5, hi5 = (5.0, 5.0, 4.0, -4.0 / 3.0, -4.0 / 3.0), (100.0, 20.0, 5.3, 10.0 / 3.0, 10.0 / 3.0)
+        spec5 = xs.sampler(lo5, hi5)
+        x5 = torch.tensor(np.asarray(lo5) + (np.asarray(hi5) - np.asarray(lo5)) * synth.uniforms((ne, 5), 404),
+                          dtype=torch.float64, device="cuda")
+        lp5 = ctx.mcmc_lnprob(hs, spec5, x5)
+        for t in range(args.warmup):
+            ctx.mcmc_step(hs, spec5, x5, lp5, u[t], acc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.warmup, nsteps):
+            ctx.mcmc_step(hs, spec5, x5, lp5, u[t], acc)
+        torch.cuda.synchronize()
+        ms_m5 = (time.perf_counter() - t0) * 1e3 / args.steps
+        result["mcmc"]["two_population"] = {"ms_per_step": round(ms_m5, 4),
+                                            "walker_evals_per_s": round(ne / (ms_m5 * 1e-3), 2),
+                                            "note": "eq. (9) walkers, prior [5,100]x[5,20]x[4,5.3]x[-4/3,10/3]^2"}
 
     if not args.no_velocity:
         # the same step with the velocity-gradient factor H / (dv_r/dr + H) in dT_b

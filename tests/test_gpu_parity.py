@@ -545,7 +545,7 @@ def test_mcmc_chain_vs_oracle(xs, dim):
         fid, nw, steps = (30.0, 15.0, np.log10(5e4)), 8, 3
         lo, hi = PRIOR3
     else:
-        specs = [(16, 32.0, 8.5, 4)]
+        specs = [(16, 32.0, 10.0, 4)]   # the fiducial leaves x_HI ~ 0.5 here
         fid, nw, steps = (70.0, 15.0, 4.7, 4 / 3, -1 / 3), 6, 2
         lo, hi = PRIOR5
     ctx = _ctx(xs)
@@ -564,7 +564,8 @@ def test_mcmc_chain_vs_oracle(xs, dim):
                                                 PHYS)
         mocks.append(ev.delta2)
         ctx.set_mock(h, ev.delta2)
-    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * (0.25 + 0.5 * synth.uniforms((nw, dim), 210 + dim))
+    # walkers around the fiducial (within 10 % of the prior range), inside the prior
+    x0 = np.asarray(fid) + (np.asarray(hi) - np.asarray(lo)) * 0.1 * (synth.uniforms((nw, dim), 210 + dim) - 0.5)
     u = synth.uniforms((steps, 2, nw // 2, 3), 310 + dim)
     spec = xs.sampler(lo, hi)
     x = torch.tensor(x0, dtype=torch.float64, device="cuda")
@@ -577,11 +578,13 @@ def test_mcmc_chain_vs_oracle(xs, dim):
         glp.append(lp.cpu().numpy().copy())
         gacc.append(acc.cpu().numpy().astype(bool))
     ox, olp, oacc = _oracle_chain(data, specs, mocks, dim, lo, hi, x0, u)
+    assert np.ptp(olp[0]) > 0.1   # a likelihood that tells the walkers apart
     print(f"[mcmc dim={dim}] accepted {int(np.sum(gacc))}/{nw * steps}; max |dlp| = "
           f"{np.max(np.abs(np.array(glp) - olp)):.2e}", flush=True)
     np.testing.assert_array_equal(np.array(gacc), oacc)
     np.testing.assert_allclose(np.array(gx), ox, rtol=1e-12)
-    np.testing.assert_allclose(np.array(glp), olp, rtol=1e-9 if dim == 3 else 1e-5)
+    # ln p to FP64 round-off (3 parameters) or to the two-population table's interpolation
+    np.testing.assert_allclose(np.array(glp), olp, rtol=1e-9 if dim == 3 else 1e-5, atol=0 if dim == 3 else 1e-6)
     ctx.close()
 
 
