@@ -678,6 +678,12 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
     T d[kNrMax];
     load_radii<T, S>(dR, N3, cell, nr, d);
     const T od = odens[cell];
+    // Every delta_R of the cell is in its register before the walker loop:
+    // otherwise the compiler, unable to see that the loads have landed after
+    // the first walker, keeps one load-counter wait per radius inside the loop
+    // for every walker (an empty asm taking the values, no instruction).
+#pragma unroll
+    for (int s = 0; s < kNrMax; ++s) asm volatile("" ::"v"(d[s]));
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
 #pragma unroll 1
