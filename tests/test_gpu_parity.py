@@ -414,6 +414,35 @@ def test_velocity_factor(xs, dtype):
     ctx.close()
 
 
+def test_velocity_256_full_size(xs):
+    """The velocity-gradient factor at 256^3 x 3 z with 64 walkers (the launch
+    configuration the benchmark times for it); one sampled walker on the z = 8
+    box checked cell by cell and bin by bin against the oracle with velocities."""
+    import torch
+    wl = synth.WORKLOADS["batched-256"]
+    boxes = synth.workload_boxes(wl, AMP)
+    walkers = synth.workload_walkers(wl)
+    phys = oracle.Physics(pk_amp=AMP, velocity=True, dvdr_max=0.2)
+    ctx = _ctx(xs, velocity=1, dvdr_max=0.2)
+    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+    ctx.prepare("f32", max_walkers=64, max_plain_radii=40)
+    pk, xhi = ctx.eval_batch(hs, walkers)
+    pk = pk.cpu().numpy()
+    xhi = xhi.cpu().numpy()
+    assert np.isfinite(pk).all() and np.all((xhi >= 0) & (xhi <= 1))
+    s0 = wl.boxes[0]
+    shared = ctx.radii(hs[0])
+    i = 11
+    w = walkers[i]
+    ev = oracle.evaluate(boxes[0], s0.box_mpc, s0.z, w, oracle.walker_radii(shared, w[1]), s0.n_bins, phys)
+    x, _ = ctx.materialize(hs[0], w)
+    flips, rel = report(f"velocity-256 w{i} z={s0.z:g}", x.cpu().numpy(), ev, pk[i, 0], xhi[i, 0])
+    assert flips <= 1e-4 and rel <= 1e-3
+    assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-4
+    ctx.close()
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ two-population efficiency (eq. 9)
 
 EDGE2 = [(70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0),   # the fiducial of Section 4
