@@ -617,8 +617,10 @@ def test_mcmc_chain_vs_oracle(xs, dim):
     ctx.close()
 
 
-def test_mcmc_256_consistency(xs):
-    """The benchmark geometry (256^3 x 3 z, FP32), 128 walkers: device-planned ln p equals
+@pytest.mark.parametrize("dim", [3, 5])
+def test_mcmc_256_consistency(xs, dim):
+    """The benchmark geometry (256^3 x 3 z, FP32), 128 walkers of the constant-efficiency
+    (dim 3) or two-population (dim 5) model drawn over the prior: device-planned ln p equals
     -chi^2/2 of the host-planned batch; after steps, walkers that did not move keep x and
     ln p, and every ln p equals a fresh evaluation of its walker."""
     import torch
@@ -633,20 +635,21 @@ def test_mcmc_256_consistency(xs):
     for i, h in enumerate(hs):
         km, _ = ctx.bins(h)
         ctx.set_mock(h, km ** 3 * fpk[0, i, :len(km)] / (2 * np.pi ** 2))
-    lo, hi = PRIOR3
+    lo, hi = PRIOR3 if dim == 3 else PRIOR5
     nw = 128
-    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * synth.uniforms((nw, 3), 220)
+    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * synth.uniforms((nw, dim), 220 if dim == 3 else 221)
     spec = xs.sampler(lo, hi)
     x = torch.tensor(x0, dtype=torch.float64, device="cuda")
     lp = ctx.mcmc_lnprob(hs, spec, x)
-    walkers = np.column_stack([x0[:, 0], x0[:, 1], 10 ** x0[:, 2]])
-    pk, _ = ctx.eval_batch(hs, walkers)
+    walkers = np.column_stack([x0[:, 0], x0[:, 1], 10 ** x0[:, 2], *x0[:, 3:].T])
+    pk, _ = (ctx.eval_batch if dim == 3 else ctx.eval_batch2)(hs, walkers)
     ref = -0.5 * ctx.chi2(hs, pk).cpu().numpy()
     np.testing.assert_allclose(lp.cpu().numpy(), ref, rtol=1e-4)
     acc = torch.zeros(nw, dtype=torch.int32, device="cuda")
     for t in range(2):
         xb, lpb = x.clone(), lp.clone()
-        ctx.mcmc_step(hs, spec, x, lp, torch.tensor(synth.uniforms((2, nw // 2, 3), 320 + t), device="cuda"), acc)
+        ctx.mcmc_step(hs, spec, x, lp, torch.tensor(synth.uniforms((2, nw // 2, 3), 320 + 10 * dim + t),
+                                                    device="cuda"), acc)
         moved = acc.cpu().numpy().astype(bool)
         assert 0 < moved.sum() < nw
         np.testing.assert_array_equal(x.cpu().numpy()[~moved], xb.cpu().numpy()[~moved])
