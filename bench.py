@@ -14,8 +14,11 @@ boxes of the walker's own radii per evaluation), Gcell-R/s, the roofline of the
 dominant kernel (HIP events on the library stream inside the timed steps,
 algorithmic bytes), the FP64 CPU oracle timed on a bounded sample, and the
 same step with the velocity-gradient factor of eq. (4) and with two-population
-walkers (the efficiency of eq. (9)), and the rate of the device-resident
-ensemble sampler (Section 2.3) driving the same evaluation.
+walkers (the efficiency of eq. (9)), the rate of the device-resident
+ensemble sampler (Section 2.3) driving the same evaluation, the steady state
+with 256 and 1024 walkers drawn from the priors on the same boxes, and the
+bandwidth of a plain 1 GiB device-to-device copy (the practical HBM ceiling
+beside the 8 TB/s peak).
 """
 from __future__ import annotations
 
@@ -89,6 +92,8 @@ def main():
     ap.add_argument("--no-mcmc", action="store_true", help="skip the ensemble-sampler loop")
     ap.add_argument("--no-two-population", action="store_true",
                     help="skip the variant with the two-population efficiency of eq. (9)")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip the steady state at 256 and 1024 walkers and the copy ceiling")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -162,6 +167,44 @@ def main():
     torch.cuda.synchronize()
     ms_steady = (time.perf_counter() - t0) * 1e3 / args.steps
 
+    # the same steady state with more walkers on the same boxes (groups of 64 in turn)
+    walker_scaling = None
+    copy_ceiling = None
+    if not args.no_scaling:
+        log("timing the steady state at 256 and 1024 walkers")
+        walker_scaling = {}
+        for wn in (256, 1024):
+            ws = synth.draw_walkers(wn, 1000 + wn)
+            pkw = torch.empty((wn, len(hs), nbmax), dtype=torch.float64, device="cuda")
+            xw = torch.empty((wn, len(hs)), dtype=torch.float64, device="cuda")
+            cw = torch.empty(wn, dtype=torch.float64, device="cuda")
+            ctx.eval_batch(hs, ws, pkw, xw)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.eval_batch(hs, ws, pkw, xw)
+                ctx.chi2(hs, pkw, cw)
+            torch.cuda.synchronize()
+            ms_w = (time.perf_counter() - t0) * 1e3 / reps
+            walker_scaling[str(wn)] = {"ms_per_batch": round(ms_w, 3),
+                                       "walker_evals_per_s": round(wn / (ms_w * 1e-3), 2)}
+        # practical HBM ceiling: a plain device-to-device copy of 1 GiB (reads + writes)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_c = e0.elapsed_time(e1) / 5
+        copy_ceiling = {"GBps": round(2 * a.numel() * 4 / (ms_c * 1e-3) / 1e9, 1),
+                        "frac_of_peak": round(2 * a.numel() * 4 / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "kind": "torch device-to-device copy of 1 GiB (read + write bytes)"}
+        del a, b
+
     # ionisation work: sum over walkers and boxes of N^3 x (radii the walker filters at)
     cellR = 0.0
     for h, s in zip(hs, wl.boxes):
@@ -215,7 +258,9 @@ def main():
                    "walkers": nw, "boxes": len(hs), "grid": wl.boxes[0].n, "parallelism": "single GPU"},
         "gcell_r_per_s": round(cellR / (ms_step * 1e-3) / 1e9, 2),
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
-                         "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2)},
+                         "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2),
+                         "more_walkers": walker_scaling},
+        "hbm_copy_ceiling": copy_ceiling,
         "plain_per_walker": None if ms_plain is None else
         {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
         "kernels": kernels,
