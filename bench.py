@@ -239,6 +239,10 @@ def main():
     alu_bound = achieved_ops / VALU_PEAK_TOPS > achieved / HBM_PEAK_GBS
     kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
                    "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items() if v["launches"]}
+    # the whole step: algorithmic bytes of every kernel over the step's wall time
+    step_bytes = sum(v["bytes"] for v in prof.values()) / args.steps
+    step_hbm = {"algorithmic_GB": round(step_bytes / 1e9, 3), "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+                "frac_of_peak": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     result = {
         "metric": "walker likelihood evals/sec at 256^3 x 3 z; ionization Gcell-R/s; %HBM peak",
@@ -260,6 +264,7 @@ def main():
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
                          "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2),
                          "more_walkers": walker_scaling},
+        "step_hbm": step_hbm,
         "hbm_copy_ceiling": copy_ceiling,
         "plain_per_walker": None if ms_plain is None else
         {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
