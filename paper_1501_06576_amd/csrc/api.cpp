@@ -58,10 +58,13 @@ struct BoxRec {
   int storage = 0;
   int rbatch = 1;             // radii smoothed per launch
   std::vector<long> cut;      // (n2max, kmax) per ladder radius, then one pair keeping every mode
+  std::vector<int32_t> live;  // smoothing z pass: (radius << 24) | tile of the tiles inside each radius's disk
+  std::vector<long> live_off; // first entry of radius j in live (nr + 1 offsets)
   bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
   size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_od = 0, off_dR = 0, off_like = 0;
   size_t off_slots = 0;       // SlotPlan2 per radius slot, for planning from device walker parameters
+  size_t off_live = 0;        // the live-tile list of the smoothing z pass
   xs21::BoxPlan bplan{};      // the box's planning scalars (kernel argument)
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
@@ -273,6 +276,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     off += align_up(b.nbins * 8);
     b.off_cut = off;
     off += align_up(b.cut.size() * sizeof(long));
+    b.off_live = off;
+    off += align_up(b.live.size() * sizeof(int32_t));
     b.off_like = off;
     off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
     b.off_slots = off;
@@ -420,8 +425,11 @@ hipError_t forward3d(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* r
 // the z pass the columns with ny^2 + kx^2 <= n2max, the y pass the columns
 // kx <= kmax, the x pass the entries kx <= kmax of each row; only the delta_R
 // write is full size.
+// With tiles != nullptr the z pass runs over that list of ntiles live tiles
+// (entries of radii r0 .. r0 + cnt - 1) instead of a block per tile and radius.
 hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* hat, unsigned char* tmp,
-                        const long* cut_dev, const long* cut_host, int cnt, int storage, unsigned char* out) {
+                        const long* cut_dev, const long* cut_host, int cnt, int storage, unsigned char* out,
+                        const int32_t* tiles = nullptr, long ntiles = 0, int r0 = 0) {
   const long n = b.n, hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells());
@@ -439,6 +447,9 @@ hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void
     xb += (kmax + 1) * n * n * 2 * rs + cells * store_size(storage);
   }
   hipError_t e = timed(c, st, XS21_K_AXIS_INV, zb, [&] {
+    if (tiles)
+      return xs21::launch_axis_live(b.dtype, b.n, hat, tmp, n * hp, tiles, ntiles, r0, cut_dev, sstride, tw, kNtab,
+                                    st);
     return xs21::launch_axis(b.dtype, b.n, +1, 1, hat, tmp, 1, n * hp, n * hp, cut_dev, cnt, 0, sstride, tw, kNtab,
                              st);
   });
@@ -465,7 +476,9 @@ hipError_t smooth_box(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
   for (int j = 0; j < b.nr(); j += b.rbatch) {
     const int cnt = std::min(b.rbatch, b.nr() - j);
     unsigned char* out = c->ws + b.off_dR + static_cast<size_t>(j) * b.cells() * store_size(b.storage);
-    e = smooth_batch(c, st, b, hat, tmp, cut_dev + 2 * j, b.cut.data() + 2 * j, cnt, b.storage, out);
+    const long t0 = b.live_off[j], t1 = b.live_off[j + cnt];
+    e = smooth_batch(c, st, b, hat, tmp, cut_dev + 2 * j, b.cut.data() + 2 * j, cnt, b.storage, out,
+                     reinterpret_cast<const int32_t*>(c->ws + b.off_live) + t0, t1 - t0, j);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -688,6 +701,27 @@ xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_d
   for (size_t j = 0; j < b.radii.size(); ++j) cut_pair(b, b.radii[j], &b.cut[2 * j]);
   b.cut[2 * b.radii.size()] = 3L * (n / 2) * (n / 2) + 1;  // every mode
   b.cut[2 * b.radii.size() + 1] = n / 2;
+  {
+    // tiles of the smoothing z pass with a column (ky, kx) inside the disk
+    // ny^2 + kx^2 <= n2max of each radius (padding columns kx > n/2 never are)
+    const long hp = xs21::half_pitch(n), h = n / 2 + 1, ti = xs21::axis_tile_cols(n), cols = n * hp;
+    const long ntile = (cols + ti - 1) / ti;
+    if (ti < 1 || ntile >= (1L << 24) || b.nr() >= 128)
+      return fail(XS21_EUNSUPPORTED, "smoothing tile list out of range (n = %d)", n);
+    b.live_off.assign(1, 0);
+    for (int r = 0; r < b.nr(); ++r) {
+      const long n2 = b.cut[2 * r];
+      for (long t = 0; t < ntile; ++t) {
+        bool any = false;
+        for (long i = t * ti; i < std::min(cols, (t + 1) * ti) && !any; ++i) {
+          const long ky = i / hp, kx = i % hp, ny = ky < n / 2 ? ky : ky - n;
+          any = kx < h && ny * ny + kx * kx <= n2;
+        }
+        if (any) b.live.push_back(static_cast<int32_t>((static_cast<long>(r) << 24) | t));
+      }
+      b.live_off.push_back(static_cast<long>(b.live.size()));
+    }
+  }
   b.bintab = xs21::plan::bins(n, n_bins);
   xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
   if (on_device) {
@@ -785,6 +819,8 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_counts, b.counts.data(), b.nbins * 8, hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_cut, b.cut.data(), b.cut.size() * sizeof(long), hipMemcpyHostToDevice,
                                  ctx->stream));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_live, b.live.data(), b.live.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, ctx->stream));
     {
       const auto slots = xs21::plan::slots2(ctx->phys, b.z, b.radii);
       b.bplan = xs21::plan::box_plan(ctx->phys, b.z, b.nr());

@@ -238,6 +238,9 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
 // MODE 4: inverse z pass (inner index as in MODE 1) of the line-of-sight
 //   velocity gradient: each mode is weighted by nz^2 / |n|^2 on load (0 for
 //   the mean and the padding columns).
+// MODE 5: MODE 1 over a list of live tiles: block b takes entry
+//   tiles[b] = (radius << 24) | tile, radius counted from r0, so that no block
+//   is launched for a tile outside its radius's disk.
 // ---------------------------------------------------------------------------
 // |n|^2 without the z part of flat column i = y * HP + kx of a padded half
 // spectrum; padding columns (kx > N/2) get a value above every cutoff.
@@ -253,20 +256,28 @@ __device__ __forceinline__ int column_n2(long i) {
 template <typename T, int N, int DIR, int MODE>
 __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, cplx<T>* dst, long inner, long ilim,
                                                            const long* __restrict__ cut, long sstride, long dstride,
-                                                           long nslices, const cplx<T>* __restrict__ tw, int tstride) {
+                                                           long nslices, const cplx<T>* __restrict__ tw, int tstride,
+                                                           const int32_t* __restrict__ tiles, int r0) {
   using A = AxisShape<N>;
+  constexpr bool DISK = MODE == 1 || MODE == 5;  // z pass of a smoothing
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
   const int t = threadIdx.x;
-  // blockIdx.z selects one smoothing radius of a batch: its own cutoff
-  // (n2max, kmax) and its own slice of src / dst
-  long n2max = 0;
-  if constexpr (MODE == 1 || MODE == 2) {
-    n2max = cut[2 * blockIdx.z];
-    if constexpr (MODE == 2) ilim = min(ilim, cut[2 * blockIdx.z + 1] + 1);
+  // blockIdx.z (or the list entry) selects one smoothing radius of a batch:
+  // its own cutoff (n2max, kmax) and its own slice of src / dst
+  long zr = blockIdx.z, bx = blockIdx.x;
+  if constexpr (MODE == 5) {
+    const int32_t e = tiles[blockIdx.x];
+    zr = (e >> 24) - r0;
+    bx = e & 0xffffff;
   }
-  src += blockIdx.z * sstride;
-  dst += blockIdx.z * dstride;
+  long n2max = 0;
+  if constexpr (DISK || MODE == 2) {
+    n2max = cut[2 * zr];
+    if constexpr (MODE == 2) ilim = min(ilim, cut[2 * zr + 1] + 1);
+  }
+  src += zr * sstride;
+  dst += zr * dstride;
   if constexpr (MODE == 3) {
     // gathered single columns: column c of the tile is slice blockIdx.x * TI + c
     const long outer = nslices;
@@ -286,7 +297,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     return;
   }
   const long base = static_cast<long>(blockIdx.y) * N * inner;
-  const long i0 = static_cast<long>(blockIdx.x) * A::TI;
+  const long i0 = bx * A::TI;
   if (i0 >= ilim) return;  // block-uniform
   if constexpr (MODE == 1) {
     bool any = false;  // block-uniform
@@ -308,7 +319,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     const long nn = n < N / 2 ? n : n - N;
     bool live = i < ilim;
     T wgt = T(1);
-    if constexpr (MODE == 1) live = live && column_n2<N>(i) + nn * nn <= n2max;
+    if constexpr (DISK) live = live && column_n2<N>(i) + nn * nn <= n2max;
     if constexpr (MODE == 2) live = live && nn * nn + i * i <= n2max;
     if constexpr (MODE == 4) {
       const int c2 = column_n2<N>(i);
@@ -330,7 +341,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     const int n = l / A::TI, c = l % A::TI;
     const long i = i0 + c;
     bool keep = i < ilim;
-    if constexpr (MODE == 1) keep = keep && column_n2<N>(i) <= n2max;
+    if constexpr (DISK) keep = keep && column_n2<N>(i) <= n2max;
     if (keep) dst[base + n * inner + i] = lds[l];
   }
 }
@@ -984,25 +995,51 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
           if (ilim > full) {
             const dim3 g2(static_cast<unsigned>((outer + A::TI - 1) / A::TI), 1, 1);
             hipLaunchKernelGGL((k_axis<T, N, -1, 3>), g2, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride,
-                               dstride, outer, tp, ts);
+                               dstride, outer, tp, ts, nullptr, 0);
           }
         } else {
           hipLaunchKernelGGL((k_axis<T, N, -1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride,
-                             dstride, outer, tp, ts);
+                             dstride, outer, tp, ts, nullptr, 0);
         }
       } else if (mode == 1) {
         hipLaunchKernelGGL((k_axis<T, N, +1, 1>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
-                           outer, tp, ts);
+                           outer, tp, ts, nullptr, 0);
       } else if (mode == 2) {
         hipLaunchKernelGGL((k_axis<T, N, +1, 2>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
-                           outer, tp, ts);
+                           outer, tp, ts, nullptr, 0);
       } else if (mode == 4) {
         hipLaunchKernelGGL((k_axis<T, N, +1, 4>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
-                           outer, tp, ts);
+                           outer, tp, ts, nullptr, 0);
       } else {
         hipLaunchKernelGGL((k_axis<T, N, +1, 0>), grid, dim3(A::NT), 0, s, sp, dp, inner, ilim, cut, sstride, dstride,
-                           outer, tp, ts);
+                           outer, tp, ts, nullptr, 0);
       }
+      return hipGetLastError();
+    });
+  });
+}
+
+int axis_tile_cols(int n) {
+  int ti = 0;
+  (void)with_n(n, [&](auto nc) {
+    ti = AxisShape<decltype(nc)::value>::TI;
+    return hipSuccess;
+  });
+  return ti;
+}
+
+hipError_t launch_axis_live(int dtype, int n, const void* src, void* dst, long inner, const int32_t* tiles,
+                            long ntiles, int r0, const long* cut, long dstride, const void* tw, int ntab,
+                            hipStream_t s) {
+  if (ntiles < 1 || ntiles > 0x7fffffffL || !tiles || !cut || r0 < 0) return hipErrorInvalidValue;
+  return with_real(dtype, [&](auto tv) {
+    using T = decltype(tv);
+    return with_n(n, [&](auto nc) {
+      constexpr int N = decltype(nc)::value;
+      using A = AxisShape<N>;
+      hipLaunchKernelGGL((k_axis<T, N, +1, 5>), dim3(static_cast<unsigned>(ntiles)), dim3(A::NT), 0, s,
+                         static_cast<const cplx<T>*>(src), static_cast<cplx<T>*>(dst), inner, inner, cut, 0L, dstride,
+                         1L, static_cast<const cplx<T>*>(tw), ntab / N, tiles, r0);
       return hipGetLastError();
     });
   });

@@ -47,6 +47,17 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
 hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, void* dst, long outer, long inner,
                        long ilim, const long* cut, int batch, long sstride, long dstride, const void* tw, int ntab,
                        hipStream_t s);
+// Columns per tile of the strided passes at size n (tile t covers flat
+// columns t * cols .. t * cols + cols - 1 of a padded half spectrum).
+int axis_tile_cols(int n);
+// Mode 1 of launch_axis over a list of live tiles only: ntiles entries
+// tiles[k] = (r << 24) | tile, each a tile with at least one column inside
+// the disk |n|^2 <= cut[2 (r - r0)] of radius r of the batch starting at r0;
+// radius r - r0 writes dst + (r - r0) * dstride.  src, inner and cut as in
+// mode 1 (one source spectrum for every radius).
+hipError_t launch_axis_live(int dtype, int n, const void* src, void* dst, long inner, const int32_t* tiles,
+                            long ntiles, int r0, const long* cut, long dstride, const void* tw, int ntab,
+                            hipStream_t s);
 // Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] (kx < n/2)
 // and their Nyquist planes nyq[outer][ky][z], fused with |X|^2 binning into
 // part[outer][parts][nbins] (FP64); parts in [1, bins_tiles(n)], normally
