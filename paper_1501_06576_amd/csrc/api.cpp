@@ -60,11 +60,14 @@ struct BoxRec {
   std::vector<long> cut;      // (n2max, kmax) per ladder radius, then one pair keeping every mode
   std::vector<int32_t> live;  // smoothing z pass: (radius << 24) | tile of the tiles inside each radius's disk
   std::vector<long> live_off; // first entry of radius j in live (nr + 1 offsets)
+  std::vector<int32_t> live_y;   // smoothing y pass: (radius << 24) | tile of the kx tiles up to each kmax
+  std::vector<long> live_y_off;  // first entry of radius j in live_y
   bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
   size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_od = 0, off_dR = 0, off_like = 0;
   size_t off_slots = 0;       // SlotPlan2 per radius slot, for planning from device walker parameters
   size_t off_live = 0;        // the live-tile list of the smoothing z pass
+  size_t off_live_y = 0;      // the live-tile list of the smoothing y pass
   xs21::BoxPlan bplan{};      // the box's planning scalars (kernel argument)
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
@@ -278,6 +281,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     off += align_up(b.cut.size() * sizeof(long));
     b.off_live = off;
     off += align_up(b.live.size() * sizeof(int32_t));
+    b.off_live_y = off;
+    off += align_up(b.live_y.size() * sizeof(int32_t));
     b.off_like = off;
     off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
     b.off_slots = off;
@@ -426,10 +431,12 @@ hipError_t forward3d(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* r
 // kx <= kmax, the x pass the entries kx <= kmax of each row; only the delta_R
 // write is full size.
 // With tiles != nullptr the z pass runs over that list of ntiles live tiles
-// (entries of radii r0 .. r0 + cnt - 1) instead of a block per tile and radius.
+// (entries of radii r0 .. r0 + cnt - 1) instead of a block per tile and radius,
+// and the y pass over ytiles likewise.
 hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void* hat, unsigned char* tmp,
                         const long* cut_dev, const long* cut_host, int cnt, int storage, unsigned char* out,
-                        const int32_t* tiles = nullptr, long ntiles = 0, int r0 = 0) {
+                        const int32_t* tiles = nullptr, long ntiles = 0, int r0 = 0,
+                        const int32_t* ytiles = nullptr, long nytiles = 0) {
   const long n = b.n, hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells());
@@ -455,6 +462,9 @@ hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void
   });
   if (e != hipSuccess) return e;
   e = timed(c, st, XS21_K_AXIS_INV, yb, [&] {
+    if (ytiles)
+      return xs21::launch_axis_live_y(b.dtype, b.n, tmp, hp, kmax_all + 1, ytiles, nytiles, r0, cut_dev, sstride, tw,
+                                      kNtab, st);
     return xs21::launch_axis(b.dtype, b.n, +1, 2, tmp, tmp, n, hp, kmax_all + 1, cut_dev, cnt, sstride, sstride, tw,
                              kNtab, st);
   });
@@ -477,8 +487,10 @@ hipError_t smooth_box(xs21_ctx* c, hipStream_t st, const BoxRec& b) {
     const int cnt = std::min(b.rbatch, b.nr() - j);
     unsigned char* out = c->ws + b.off_dR + static_cast<size_t>(j) * b.cells() * store_size(b.storage);
     const long t0 = b.live_off[j], t1 = b.live_off[j + cnt];
+    const long y0 = b.live_y_off[j], y1 = b.live_y_off[j + cnt];
     e = smooth_batch(c, st, b, hat, tmp, cut_dev + 2 * j, b.cut.data() + 2 * j, cnt, b.storage, out,
-                     reinterpret_cast<const int32_t*>(c->ws + b.off_live) + t0, t1 - t0, j);
+                     reinterpret_cast<const int32_t*>(c->ws + b.off_live) + t0, t1 - t0, j,
+                     reinterpret_cast<const int32_t*>(c->ws + b.off_live_y) + y0, y1 - y0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -721,6 +733,13 @@ xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_d
       }
       b.live_off.push_back(static_cast<long>(b.live.size()));
     }
+    // y pass: the kx tiles t with t * ti <= kmax of each radius
+    b.live_y_off.assign(1, 0);
+    for (int r = 0; r < b.nr(); ++r) {
+      for (long t = 0; t * ti <= b.cut[2 * r + 1]; ++t)
+        b.live_y.push_back(static_cast<int32_t>((static_cast<long>(r) << 24) | t));
+      b.live_y_off.push_back(static_cast<long>(b.live_y.size()));
+    }
   }
   b.bintab = xs21::plan::bins(n, n_bins);
   xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
@@ -820,6 +839,8 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_cut, b.cut.data(), b.cut.size() * sizeof(long), hipMemcpyHostToDevice,
                                  ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_live, b.live.data(), b.live.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_live_y, b.live_y.data(), b.live_y.size() * sizeof(int32_t),
                                  hipMemcpyHostToDevice, ctx->stream));
     {
       const auto slots = xs21::plan::slots2(ctx->phys, b.z, b.radii);

@@ -241,6 +241,9 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
 // MODE 5: MODE 1 over a list of live tiles: block b takes entry
 //   tiles[b] = (radius << 24) | tile, radius counted from r0, so that no block
 //   is launched for a tile outside its radius's disk.
+// MODE 6: MODE 2 over a list of live column tiles: blockIdx.x takes entry
+//   tiles[blockIdx.x] = (radius << 24) | tile as above (tiles with kx <= kmax
+//   of that radius), blockIdx.y the slice.
 // ---------------------------------------------------------------------------
 // |n|^2 without the z part of flat column i = y * HP + kx of a padded half
 // spectrum; padding columns (kx > N/2) get a value above every cutoff.
@@ -260,21 +263,22 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
                                                            const int32_t* __restrict__ tiles, int r0) {
   using A = AxisShape<N>;
   constexpr bool DISK = MODE == 1 || MODE == 5;  // z pass of a smoothing
+  constexpr bool YPASS = MODE == 2 || MODE == 6;  // y pass of a smoothing
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
   const int t = threadIdx.x;
   // blockIdx.z (or the list entry) selects one smoothing radius of a batch:
   // its own cutoff (n2max, kmax) and its own slice of src / dst
   long zr = blockIdx.z, bx = blockIdx.x;
-  if constexpr (MODE == 5) {
+  if constexpr (MODE == 5 || MODE == 6) {
     const int32_t e = tiles[blockIdx.x];
     zr = (e >> 24) - r0;
     bx = e & 0xffffff;
   }
   long n2max = 0;
-  if constexpr (DISK || MODE == 2) {
+  if constexpr (DISK || YPASS) {
     n2max = cut[2 * zr];
-    if constexpr (MODE == 2) ilim = min(ilim, cut[2 * zr + 1] + 1);
+    if constexpr (YPASS) ilim = min(ilim, cut[2 * zr + 1] + 1);
   }
   src += zr * sstride;
   dst += zr * dstride;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
     bool live = i < ilim;
     T wgt = T(1);
     if constexpr (DISK) live = live && column_n2<N>(i) + nn * nn <= n2max;
-    if constexpr (MODE == 2) live = live && nn * nn + i * i <= n2max;
+    if constexpr (YPASS) live = live && nn * nn + i * i <= n2max;
     if constexpr (MODE == 4) {
       const int c2 = column_n2<N>(i);
       const long k2 = c2 + nn * nn;
@@ -1040,6 +1044,24 @@ hipError_t launch_axis_live(int dtype, int n, const void* src, void* dst, long i
       hipLaunchKernelGGL((k_axis<T, N, +1, 5>), dim3(static_cast<unsigned>(ntiles)), dim3(A::NT), 0, s,
                          static_cast<const cplx<T>*>(src), static_cast<cplx<T>*>(dst), inner, inner, cut, 0L, dstride,
                          1L, static_cast<const cplx<T>*>(tw), ntab / N, tiles, r0);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_axis_live_y(int dtype, int n, void* data, long inner, long ilim, const int32_t* tiles, long ntiles,
+                              int r0, const long* cut, long stride, const void* tw, int ntab, hipStream_t s) {
+  if (ntiles < 1 || ntiles > 0x7fffffffL || !tiles || !cut || r0 < 0 || ilim < 1 || ilim > inner)
+    return hipErrorInvalidValue;
+  return with_real(dtype, [&](auto tv) {
+    using T = decltype(tv);
+    return with_n(n, [&](auto nc) {
+      constexpr int N = decltype(nc)::value;
+      using A = AxisShape<N>;
+      auto* dp = static_cast<cplx<T>*>(data);
+      hipLaunchKernelGGL((k_axis<T, N, +1, 6>), dim3(static_cast<unsigned>(ntiles), static_cast<unsigned>(N)),
+                         dim3(A::NT), 0, s, dp, dp, inner, ilim, cut, stride, stride, 1L,
+                         static_cast<const cplx<T>*>(tw), ntab / N, tiles, r0);
       return hipGetLastError();
     });
   });

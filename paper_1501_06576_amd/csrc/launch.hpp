@@ -58,6 +58,12 @@ int axis_tile_cols(int n);
 hipError_t launch_axis_live(int dtype, int n, const void* src, void* dst, long inner, const int32_t* tiles,
                             long ntiles, int r0, const long* cut, long dstride, const void* tw, int ntab,
                             hipStream_t s);
+// Mode 2 of launch_axis (in place, slices [n][n][inner] at data + (r - r0) *
+// stride) over a list of live column tiles: tiles[k] = (r << 24) | tile with
+// tile * cols <= cut[2 (r - r0) + 1] (kmax of radius r); every z slice of
+// each listed tile is transformed.  ilim: the batch's largest kmax + 1.
+hipError_t launch_axis_live_y(int dtype, int n, void* data, long inner, long ilim, const int32_t* tiles, long ntiles,
+                              int r0, const long* cut, long stride, const void* tw, int ntab, hipStream_t s);
 // Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] (kx < n/2)
 // and their Nyquist planes nyq[outer][ky][z], fused with |X|^2 binning into
 // part[outer][parts][nbins] (FP64); parts in [1, bins_tiles(n)], normally
