@@ -16,7 +16,8 @@ algorithmic bytes), the FP64 CPU oracle timed on a bounded sample, and the
 same step with the velocity-gradient factor of eq. (4) and with two-population
 walkers (the efficiency of eq. (9)), the rate of the device-resident
 ensemble sampler (Section 2.3) driving the same evaluation, the steady state
-with 256 and 1024 walkers drawn from the priors on the same boxes, and the
+with 256 and 1024 walkers drawn from the priors on the same boxes, the shared
+smoothing stage alone (smoothed cells per second), and the
 bandwidth of a plain 1 GiB device-to-device copy (the practical HBM ceiling
 beside the 8 TB/s peak).
 """
@@ -93,7 +94,8 @@ def main():
     ap.add_argument("--no-two-population", action="store_true",
                     help="skip the variant with the two-population efficiency of eq. (9)")
     ap.add_argument("--no-scaling", action="store_true",
-                    help="skip the steady state at 256 and 1024 walkers and the copy ceiling")
+                    help="skip the shared-stage timing, the steady state at 256 and 1024 walkers "
+                         "and the copy ceiling")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -166,6 +168,22 @@ def main():
         steady()
     torch.cuda.synchronize()
     ms_steady = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # the shared stage alone (a2 + a3: forward FFT and every smoothed box of the
+    # ladder, for each box), as a rate of smoothed cells N^3 x N_R
+    shared_stage = None
+    if not args.no_scaling:
+        log("timing the shared smoothing stage")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for h in hs:
+                ctx.resmooth(h)
+        torch.cuda.synchronize()
+        ms_shared = (time.perf_counter() - t0) * 1e3 / args.steps
+        shared_cells = sum(float(s.n) ** 3 * len(ctx.radii(h)) for h, s in zip(hs, wl.boxes))
+        shared_stage = {"ms_per_step": round(ms_shared, 4), "boxes": len(hs),
+                        "gcell_r_per_s": round(shared_cells / (ms_shared * 1e-3) / 1e9, 2)}
 
     # the same steady state with more walkers on the same boxes (groups of 64 in turn)
     walker_scaling = None
@@ -264,6 +282,7 @@ def main():
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
                          "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2),
                          "more_walkers": walker_scaling},
+        "shared_stage": shared_stage,
         "step_hbm": step_hbm,
         "hbm_copy_ceiling": copy_ceiling,
         "plain_per_walker": None if ms_plain is None else
