@@ -79,6 +79,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or "" where it cannot be read."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +452,14 @@ def main():
         result["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "walker-evals/s", "cores":
                                   oracle.FFT_WORKERS, "kind": "oracle",
                                   "sample": f"1 walker (the batch's first) x {len(hs)} boxes ({wl.boxes[0].n}^3, "
-                                            f"{'/'.join(str(n) for n in nrad)} radii) in {dt:.2f} s"}
+                                            f"{'/'.join(str(n) for n in nrad)} radii) in {dt:.2f} s",
+                                  "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+    props = torch.cuda.get_device_properties(0)
+    result["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                        "compute_units": props.multi_processor_count,
+                        "lds_per_block_bytes": props.shared_memory_per_block,
+                        "l2_bytes": getattr(props, "L2_cache_size", None),
+                        "memory_gib": round(props.total_memory / 2 ** 30, 1)}
     ctx.close()
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
