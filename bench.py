@@ -12,14 +12,16 @@ Also reported: the steady-state rate with the smoothed boxes resident (the MCMC
 loop), the plain per-walker form (recomputes the forward FFT and all smoothed
 boxes of the walker's own radii per evaluation), Gcell-R/s, the roofline of the
 dominant kernel (HIP events on the library stream inside the timed steps,
-algorithmic bytes), the FP64 CPU oracle timed on a bounded sample, and the
-same step with the velocity-gradient factor of eq. (4) and with two-population
-walkers (the efficiency of eq. (9)), the rate of the device-resident
-ensemble sampler (Section 2.3) driving the same evaluation, the steady state
-with 256 and 1024 walkers drawn from the priors on the same boxes, the shared
-smoothing stage alone (smoothed cells per second), and the
-bandwidth of a plain 1 GiB device-to-device copy (the practical HBM ceiling
-beside the 8 TB/s peak).
+algorithmic bytes against the 8 TB/s HBM peak; VALU instructions from the
+committed counter run against the vector instruction rate as a second view),
+the project's own HBM probes (read, write, copy and the binning pass's strided
+tiles) as practical ceilings, the FP64 CPU oracle timed on a bounded sample,
+the same step with the velocity-gradient factor of eq. (4) and with
+two-population walkers (eq. (9)), the device-resident ensemble sampler
+(Section 2.3), the steady state with 256 and 1024 walkers, the shared smoothing
+stage alone, the plain single-walker workloads (64^3 FP64, 128^3 x 3 z FP32)
+with the oracle timed beside them, the uneven 128^3/256^3 BF16 workload with
+256 walkers, and the 512^3 x 3 z workload with 1024 walkers.
 """
 from __future__ import annotations
 
@@ -38,21 +40,23 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Vector ALU issue peak without packed FP32 (disabled in this build): 256 CUs x
-# 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations per second.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Vector ALU instruction rate without packed FP32 (disabled in this build): 256
+# CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions per second (a
+# wave64 VALU instruction occupies a SIMD for 4 cycles).  Used for the
+# secondary ALU view: SQ_INSTS_VALU x 64 lanes per launch over the launch time.
+VALU_PEAK_TLANES = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_FILE = os.path.join(ROOT, "profiles", "valu.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 FIDUCIAL = (30.0, 15.0, 5e4)  # zeta, R_mfp [Mpc], T_vir [K] of the mock
 # zeta0, R_mfp [Mpc], T_feed [K], alpha, beta: the two-population fiducial of Section 4
 FIDUCIAL2 = (70.0, 15.0, 10 ** 4.7, 4.0 / 3.0, -1.0 / 3.0)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-
 
 # Sources of the path's kernels (the likelihood epilogue lives apart).
 KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "wave.hpp", "common.hpp", "launch.hpp")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the path's kernel sources; traffic figures are only reused for the same code."""
+    """Hash of the path's kernel sources; counter figures are only reused for the same code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1501_06576_amd", "csrc")
     for name in KERNEL_SOURCES:
@@ -61,18 +65,34 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None if
-    the kernels changed since those counters were taken."""
+def _profile_json(path: str, workload: str):
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    return t
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of kernel class `kernel` from the committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE scaled by the probes' readings), or
+    None if the kernels changed since those counters were taken."""
+    t = _profile_json(TRAFFIC_FILE, workload)
+    if t is None or kernel not in t.get("kernels", {}):
         return None
     return t["kernels"][kernel]["bytes_per_launch"]
+
+
+def measured_valu(kernel: str, workload: str):
+    """VALU instructions per launch of kernel class `kernel` (SQ_INSTS_VALU summed
+    over its waves) from the committed counter run, or None if the kernels changed."""
+    t = _profile_json(VALU_FILE, workload)
+    if t is None or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["valu_insts_per_launch"]
 
 
 def log(msg):
@@ -91,6 +111,183 @@ def cpu_model() -> str:
     return ""
 
 
+def describe(wl, nw):
+    geos = {}
+    for s in wl.boxes:
+        geos.setdefault((s.n, s.box_mpc), []).append(s.z)
+    parts = [f"{n}^3 / {L:g} Mpc at z=" + ",".join(f"{z:g}" for z in zs) for (n, L), zs in geos.items()]
+    return f"{wl.name}: {len(wl.boxes)} boxes ({'; '.join(parts)}), {nw} walkers, {wl.storage} smoothed boxes"
+
+
+def roofline(prof, steps, workload):
+    """Roofline of the dominant kernel class over the timed launches: algorithmic
+    bytes per launch over its average launch time against the HBM peak, and the
+    VALU instruction rate from the committed counters beside it."""
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    n = max(d["launches"], 1)
+    avg_ms = d["ms"] / n
+    bytes_launch = d["bytes"] / n
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    valu = measured_valu(dom, workload)
+    out = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, workload),
+           "avg_launch_ms": round(avg_ms, 5), "launches_timed": d["launches"],
+           "algorithmic_bytes_per_launch": bytes_launch, "source_hash": kernel_source_hash()}
+    if valu is not None:
+        lanes = valu * 64 / (avg_ms * 1e-3) / 1e12
+        out["valu"] = {"insts_per_launch": valu, "achieved": round(lanes, 3), "peak": round(VALU_PEAK_TLANES, 2),
+                       "unit": "T lane-instructions/s", "frac": round(lanes / VALU_PEAK_TLANES, 4)}
+    else:
+        out["valu"] = None
+    return out
+
+
+def kernel_table(prof, steps):
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": v["launches"] / steps,
+                "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items() if v["launches"]}
+
+
+def cell_radii(ctx, hs, specs, walkers):
+    """Sum over walkers and boxes of N^3 x (radii the walker filters at)."""
+    tot = 0.0
+    for h, s in zip(hs, specs):
+        shared = np.array(ctx.radii(h))
+        for w in walkers:
+            tot += float(s.n) ** 3 * (np.count_nonzero(shared[:-1] <= w[1]) + 1)
+    return tot
+
+
+class Batch:
+    """A prepared context over one workload's boxes with a mock for the chi^2 epilogue."""
+
+    def __init__(self, xs, torch, wl, amp, walkers, phys_kw=None, group=64):
+        self.torch = torch
+        self.wl = wl
+        log(f"workload {wl.name}: generating {len(wl.boxes)} boxes")
+        self.boxes = synth.workload_boxes(wl, amp)
+        self.walkers = walkers
+        self.nw = len(walkers)
+        self.ctx = xs.Context(0, phys=xs.physics(pk_amp=amp, **(phys_kw or {})))
+        self.hs = [self.ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(self.boxes, wl.boxes)]
+        self.ctx.prepare(wl.storage, max_walkers=min(self.nw, group), max_plain_radii=40)
+        self.nbmax = max(s.n_bins for s in wl.boxes)
+        self.pk = torch.empty((self.nw, len(self.hs), self.nbmax), dtype=torch.float64, device="cuda")
+        self.xhi = torch.empty((self.nw, len(self.hs)), dtype=torch.float64, device="cuda")
+        self.chi2 = torch.empty(self.nw, dtype=torch.float64, device="cuda")
+        self.set_mock(FIDUCIAL)
+
+    def set_mock(self, fid, two=False):
+        fpk, _ = (self.ctx.eval_batch2 if two else self.ctx.eval_batch)(self.hs, [fid])
+        fpk = fpk.cpu().numpy()
+        for i, h in enumerate(self.hs):
+            km, _counts = self.ctx.bins(h)
+            self.ctx.set_mock(h, km ** 3 * fpk[0, i, : len(km)] / (2 * np.pi ** 2))
+
+    def step(self, walkers=None, two=False):
+        for h in self.hs:
+            self.ctx.resmooth(h)
+        self.steady(walkers, two)
+
+    def steady(self, walkers=None, two=False):
+        fn = self.ctx.eval_batch2 if two else self.ctx.eval_batch
+        fn(self.hs, self.walkers if walkers is None else walkers, self.pk, self.xhi)
+        self.ctx.chi2(self.hs, self.pk, self.chi2)
+
+    def timed(self, fn, reps, warmup=1):
+        for _ in range(warmup):
+            fn()
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        self.torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    def close(self):
+        self.ctx.close()
+        del self.pk, self.xhi, self.chi2
+        self.ctx = None
+        self.torch.cuda.empty_cache()
+
+
+def hbm_probes(xs, torch):
+    """The project's own HBM probes over 4 GiB (the tile probe over 50 spectra of 256^3)."""
+    ctx = xs.Context(0, phys=xs.physics())
+    out = {}
+    for kind, nbytes in (("read", 4 << 30), ("write", 4 << 30), ("copy", 4 << 30), ("tile", 3800 << 20)):
+        r = ctx.probe_bandwidth(kind, nbytes + (64 << 10), reps=5)
+        out[kind] = {"GBps": round(r["GBps"], 1), "frac_of_peak": round(r["GBps"] / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": r["bytes_per_launch"]}
+    ctx.close()
+    torch.cuda.empty_cache()
+    out["kind"] = ("project-written probe kernels (csrc/probe.hip): streaming 16-byte loads / stores, "
+                   "copy = read + write bytes, tile = the binning pass's strided 128-byte segments")
+    return out
+
+
+def section_plain_configs(xs, torch, amp, reps):
+    """The plain single-walker workloads (64^3 FP64 at z = 9; 128^3 FP32 at z = 8, 9, 10):
+    the literal per-walker method on the GPU (forward FFT and every smoothed box of the
+    walker's own radii per evaluation) and the FP64 oracle on the host, full evaluations."""
+    import oracle
+    phys = oracle.Physics(pk_amp=amp)
+    out = {}
+    for name in ("plain-f64-64", "plain-f32-128"):
+        wl = synth.WORKLOADS[name]
+        boxes = synth.workload_boxes(wl, amp)
+        w = wl.walkers[0]
+        ctx = xs.Context(0, phys=xs.physics(pk_amp=amp))
+        hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
+        ctx.prepare(wl.storage, max_walkers=1, max_plain_radii=40)
+        for h in hs:
+            ctx.eval(h, w, fields=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for h in hs:
+                ctx.eval(h, w, fields=False)
+        torch.cuda.synchronize()
+        ms_gpu = (time.perf_counter() - t0) * 1e3 / reps
+        ctx.close()
+        t0 = time.perf_counter()
+        nrad = []
+        for d, s in zip(boxes, wl.boxes):
+            radii = oracle.plain_radii(w[1], s.n, s.box_mpc, phys)
+            nrad.append(len(radii))
+            oracle.evaluate(d, s.box_mpc, s.z, w, radii, s.n_bins, phys)
+        s_orc = time.perf_counter() - t0
+        out[name] = {"workload": describe(wl, 1) + f", walker {w}, {'/'.join(map(str, nrad))} radii",
+                     "dtype": wl.dtype, "gpu_ms_per_eval": round(ms_gpu, 3),
+                     "gpu_evals_per_s": round(1e3 / ms_gpu, 2),
+                     "oracle_s_per_eval": round(s_orc, 3), "oracle_cores": oracle.FFT_WORKERS,
+                     "gpu_over_oracle": round(s_orc * 1e3 / ms_gpu, 1),
+                     "note": "one eval = the walker on every box of the workload; plain form on both sides"}
+    torch.cuda.empty_cache()
+    return out
+
+
+def section_workload(xs, torch, amp, name, reps, group=64):
+    """Full step and steady state of another workload, with its kernel table and roofline."""
+    wl = synth.WORKLOADS[name]
+    walkers = synth.workload_walkers(wl)
+    b = Batch(xs, torch, wl, amp, walkers, group=group)
+    ms_step = b.timed(b.step, reps)
+    b.ctx.profile(True)
+    ms_steady = b.timed(b.steady, reps)
+    prof = b.ctx.profile_read()
+    b.ctx.profile(False)
+    cellr = cell_radii(b.ctx, b.hs, wl.boxes, walkers)
+    out = {"workload": describe(wl, b.nw), "walkers": b.nw, "group": min(b.nw, group),
+           "ms_per_step": round(ms_step, 3), "walker_evals_per_s": round(b.nw / (ms_step * 1e-3), 2),
+           "steady_state": {"ms_per_batch": round(ms_steady, 3),
+                            "walker_evals_per_s": round(b.nw / (ms_steady * 1e-3), 2),
+                            "gcell_r_per_s": round(cellr / (ms_steady * 1e-3) / 1e9, 2)},
+           "kernels_steady": kernel_table(prof, reps), "roofline_steady": roofline(prof, reps, name)}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,10 +303,11 @@ def main():
     ap.add_argument("--no-two-population", action="store_true",
                     help="skip the variant with the two-population efficiency of eq. (9)")
     ap.add_argument("--no-scaling", action="store_true",
-                    help="skip the shared-stage timing, the steady state at 256 and 1024 walkers "
-                         "and the copy ceiling")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="end with a plain 1 GiB device copy (reference for counter scaling)")
+                    help="skip the shared-stage timing, the steady state at 256 and 1024 walkers and the probes")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (plain 64^3 / 128^3, uneven BF16 mix, 512^3)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="end with the HBM probes once each (references for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by walkers and "
@@ -124,45 +322,19 @@ def main():
         build.build()
     wl = synth.WORKLOADS[args.workload]
     amp = synth.reference_amplitude()
-    log(f"workload {wl.name}: generating {len(wl.boxes)} boxes")
-    boxes = synth.workload_boxes(wl, amp)
     walkers = synth.workload_walkers(wl)
-    nw = len(walkers)
-    ctx = xs.Context(0, phys=xs.physics(pk_amp=amp))
-    hs = [ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
-    group = min(nw, 64)
-    ctx.prepare(wl.storage, max_walkers=group, max_plain_radii=40)
-    nbmax = max(s.n_bins for s in wl.boxes)
-    pk = torch.empty((nw, len(hs), nbmax), dtype=torch.float64, device="cuda")
-    xhi = torch.empty((nw, len(hs)), dtype=torch.float64, device="cuda")
-    chi2 = torch.empty(nw, dtype=torch.float64, device="cuda")
-
-    # synthetic mock: the fiducial walker's Delta^2 on the same boxes
-    fid_pk, _ = ctx.eval_batch(hs, [FIDUCIAL])
-    fid_pk = fid_pk.cpu().numpy()
-    for i, h in enumerate(hs):
-        km, _counts = ctx.bins(h)
-        ctx.set_mock(h, km ** 3 * fid_pk[0, i, : len(km)] / (2 * np.pi ** 2))
-
-    def step():
-        for h in hs:
-            ctx.resmooth(h)
-        ctx.eval_batch(hs, walkers, pk, xhi)
-        ctx.chi2(hs, pk, chi2)
-
-    def steady():
-        ctx.eval_batch(hs, walkers, pk, xhi)
-        ctx.chi2(hs, pk, chi2)
+    b = Batch(xs, torch, wl, amp, walkers)
+    ctx, hs, nw = b.ctx, b.hs, b.nw
 
     for _ in range(args.warmup):
-        step()
+        b.step()
     torch.cuda.synchronize()
     log("timing full steps")
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        b.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
@@ -172,77 +344,34 @@ def main():
 
     # steady state: smoothed boxes resident, only the per-walker work
     log("timing steady state")
-    for _ in range(2):
-        steady()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        steady()
-    torch.cuda.synchronize()
-    ms_steady = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_steady = b.timed(b.steady, args.steps, warmup=2)
 
-    # the shared stage alone (a2 + a3: forward FFT and every smoothed box of the
-    # ladder, for each box), as a rate of smoothed cells N^3 x N_R
-    shared_stage = None
+    shared_stage = walker_scaling = probes = None
     if not args.no_scaling:
+        # the shared stage alone (a2 + a3 for each box), as smoothed cells N^3 x N_R per second
         log("timing the shared smoothing stage")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            for h in hs:
-                ctx.resmooth(h)
-        torch.cuda.synchronize()
-        ms_shared = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms_shared = b.timed(lambda: [ctx.resmooth(h) for h in hs], args.steps, warmup=0)
         shared_cells = sum(float(s.n) ** 3 * len(ctx.radii(h)) for h, s in zip(hs, wl.boxes))
         shared_stage = {"ms_per_step": round(ms_shared, 4), "boxes": len(hs),
                         "gcell_r_per_s": round(shared_cells / (ms_shared * 1e-3) / 1e9, 2)}
-
-    # the same steady state with more walkers on the same boxes (groups of 64 in turn)
-    walker_scaling = None
-    copy_ceiling = None
-    if not args.no_scaling:
         log("timing the steady state at 256 and 1024 walkers")
         walker_scaling = {}
         for wn in (256, 1024):
             ws = synth.draw_walkers(wn, 1000 + wn)
-            pkw = torch.empty((wn, len(hs), nbmax), dtype=torch.float64, device="cuda")
+            pkw = torch.empty((wn, len(hs), b.nbmax), dtype=torch.float64, device="cuda")
             xw = torch.empty((wn, len(hs)), dtype=torch.float64, device="cuda")
             cw = torch.empty(wn, dtype=torch.float64, device="cuda")
-            ctx.eval_batch(hs, ws, pkw, xw)
-            torch.cuda.synchronize()
-            reps = 3
-            t0 = time.perf_counter()
-            for _ in range(reps):
+
+            def many():
                 ctx.eval_batch(hs, ws, pkw, xw)
                 ctx.chi2(hs, pkw, cw)
-            torch.cuda.synchronize()
-            ms_w = (time.perf_counter() - t0) * 1e3 / reps
+            ms_w = b.timed(many, 3)
             walker_scaling[str(wn)] = {"ms_per_batch": round(ms_w, 3),
                                        "walker_evals_per_s": round(wn / (ms_w * 1e-3), 2)}
-        # practical HBM ceiling: a plain device-to-device copy of 1 GiB (reads + writes)
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_c = e0.elapsed_time(e1) / 5
-        copy_ceiling = {"GBps": round(2 * a.numel() * 4 / (ms_c * 1e-3) / 1e9, 1),
-                        "frac_of_peak": round(2 * a.numel() * 4 / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                        "kind": "torch device-to-device copy of 1 GiB (read + write bytes)"}
-        del a, b
+            del pkw, xw, cw
 
-    # ionisation work: sum over walkers and boxes of N^3 x (radii the walker filters at)
-    cellR = 0.0
-    for h, s in zip(hs, wl.boxes):
-        shared = np.array(ctx.radii(h))
-        for w in walkers:
-            cellR += float(s.n) ** 3 * (np.count_nonzero(shared[:-1] <= w[1]) + 1)
+    cellR = cell_radii(ctx, hs, wl.boxes, walkers)
 
-    # plain per-walker GPU form
     ms_plain = None
     if not args.no_plain and args.plain_walkers > 0:
         log("timing plain per-walker form")
@@ -257,18 +386,6 @@ def main():
         torch.cuda.synchronize()
         ms_plain = (time.perf_counter() - t0) * 1e3 / len(pw)
 
-    # roofline of the dominant kernel class over the timed steps: the bound is
-    # whichever of HBM bytes and vector ALU operations is closer to its peak
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    bytes_launch = d["bytes"] / max(d["launches"], 1)
-    ops_launch = d["ops"] / max(d["launches"], 1)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    achieved_ops = ops_launch / (avg_ms * 1e-3) / 1e12
-    alu_bound = achieved_ops / VALU_PEAK_TOPS > achieved / HBM_PEAK_GBS
-    kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
-                   "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in prof.items() if v["launches"]}
     # the whole step: algorithmic bytes of every kernel over the step's wall time
     step_bytes = sum(v["bytes"] for v in prof.values()) / args.steps
     step_hbm = {"algorithmic_GB": round(step_bytes / 1e9, 3), "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
@@ -285,32 +402,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if wl.dtype == "f32" else wl.dtype,
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {len(hs)} boxes {wl.boxes[0].n}^3 / {wl.boxes[0].box_mpc} Mpc at z="
-                               + ",".join(str(s.z) for s in wl.boxes) + f", {nw} walkers, {wl.storage} smoothed boxes",
-                   "walkers": nw, "boxes": len(hs), "grid": wl.boxes[0].n, "parallelism": "single GPU"},
+        "config": {"workload": describe(wl, nw), "walkers": nw, "boxes": len(hs), "grid": wl.boxes[0].n,
+                   "parallelism": "single GPU"},
         "gcell_r_per_s": round(cellR / (ms_step * 1e-3) / 1e9, 2),
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
                          "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2),
                          "more_walkers": walker_scaling},
         "shared_stage": shared_stage,
         "step_hbm": step_hbm,
-        "hbm_copy_ceiling": copy_ceiling,
         "plain_per_walker": None if ms_plain is None else
         {"ms_per_eval": round(ms_plain, 3), "walker_evals_per_s": round(1e3 / ms_plain, 3)},
-        "kernels": kernels,
-        "likelihood": {"chi2_min": round(float(chi2.min()), 4), "chi2_median": round(float(chi2.median()), 4),
+        "kernels": kernel_table(prof, args.steps),
+        "likelihood": {"chi2_min": round(float(b.chi2.min()), 4), "chi2_median": round(float(b.chi2.median()), 4),
                        "mock": "fiducial walker (30, 15, 5e4) on the same boxes"},
-        "roofline": ({"kernel": dom, "bound": "alu", "achieved": round(achieved_ops, 3),
-                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4),
-                      "algorithmic_ops_per_launch": ops_launch, "hbm": {"achieved": round(achieved, 1),
-                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}}
-                     if alu_bound else
-                     {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}) | {
-                     "traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 5),
-                     "algorithmic_bytes_per_launch": bytes_launch, "source_hash": kernel_source_hash()},
+        "roofline": roofline(prof, args.steps, wl.name),
     }
 
     if not args.no_mcmc:
@@ -370,104 +477,89 @@ def main():
                                             "walker_evals_per_s": round(ne / (ms_m5 * 1e-3), 2),
                                             "note": "eq. (9) walkers, prior [5,100]x[5,20]x[4,5.3]x[-4/3,10/3]^2"}
 
-    if not args.no_velocity:
-        # the same step with the velocity-gradient factor H / (dv_r/dr + H) in dT_b
-        log("timing the variant with the velocity-gradient factor")
-        vctx = xs.Context(0, phys=xs.physics(pk_amp=amp, velocity=1))
-        vhs = [vctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(boxes, wl.boxes)]
-        vctx.prepare(wl.storage, max_walkers=group, max_plain_radii=40)
-        vfid, _ = vctx.eval_batch(vhs, [FIDUCIAL])
-        vfid = vfid.cpu().numpy()
-        for i, h in enumerate(vhs):
-            km, _counts = vctx.bins(h)
-            vctx.set_mock(h, km ** 3 * vfid[0, i, : len(km)] / (2 * np.pi ** 2))
-
-        def vstep():
-            for h in vhs:
-                vctx.resmooth(h)
-            vctx.eval_batch(vhs, walkers, pk, xhi)
-            vctx.chi2(vhs, pk, chi2)
-
-        for _ in range(args.warmup):
-            vstep()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            vstep()
-        torch.cuda.synchronize()
-        ms_v = (time.perf_counter() - t0) * 1e3 / args.steps
-        result["velocity_term"] = {"ms_per_step": round(ms_v, 4), "walker_evals_per_s": round(nw / (ms_v * 1e-3), 2),
-                                   "note": "same step with dT_b times H / (dv_r/dr + H), |dv_r/dr| / H <= 0.2"}
-        vctx.close()
-
     if not args.no_two_population:
         # the same step for two-population walkers (zeta0, R_mfp, T_feed, alpha, beta)
         # drawn from their priors, against the mock of the fiducial of that model
         log("timing the two-population variant")
         walkers2 = synth.draw_walkers2(nw, synth.WALKER_SEEDS["two-population-256"])
-        fid2, _ = ctx.eval_batch2(hs, [FIDUCIAL2])
-        fid2 = fid2.cpu().numpy()
-        for i, h in enumerate(hs):
-            km, _counts = ctx.bins(h)
-            ctx.set_mock(h, km ** 3 * fid2[0, i, : len(km)] / (2 * np.pi ** 2))
-
-        def step2():
-            for h in hs:
-                ctx.resmooth(h)
-            ctx.eval_batch2(hs, walkers2, pk, xhi)
-            ctx.chi2(hs, pk, chi2)
-
-        for _ in range(args.warmup):
-            step2()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step2()
-        torch.cuda.synchronize()
-        ms_2 = (time.perf_counter() - t0) * 1e3 / args.steps
-        # one more step under the library's per-kernel event timing
+        b.set_mock(FIDUCIAL2, two=True)
+        ms_2 = b.timed(lambda: b.step(walkers2, two=True), args.steps, warmup=args.warmup)
         ctx.profile(True)
-        step2()
+        b.step(walkers2, two=True)
         prof2 = ctx.profile_read()
         ctx.profile(False)
         result["two_population"] = {
             "ms_per_step": round(ms_2, 4), "walker_evals_per_s": round(nw / (ms_2 * 1e-3), 2),
             "plan_ms_per_step": round(prof2["plan"]["ms"], 4),
             "ion_ms_per_step": round(prof2["ion"]["ms"], 4),
-            "chi2_median": round(float(chi2.median()), 4),
+            "chi2_median": round(float(b.chi2.median()), 4),
             "note": "eq. (9) walkers drawn from the priors; mock = fiducial (70, 15 Mpc, 10^4.7 K, 4/3, -1/3)"}
 
     if not args.no_cpu_baseline:
-        log("timing the FP64 CPU oracle on one walker x all boxes")
+        log("timing the FP64 CPU oracle on a bounded sample")
         import oracle
         phys = oracle.Physics(pk_amp=amp)
         w = walkers[0]
         nrad = []
+        # one walker on every box (at 512^3: on the first box only, tens of seconds per box)
+        sample = list(zip(hs, b.boxes, wl.boxes))
+        if wl.boxes[0].n >= 512:
+            sample = sample[:1]
         t0 = time.perf_counter()
-        for h, d, s in zip(hs, boxes, wl.boxes):
+        for h, d, s in sample:
             radii = oracle.walker_radii(ctx.radii(h), w[1])
             nrad.append(len(radii))
             oracle.evaluate(d, s.box_mpc, s.z, w, radii, s.n_bins, phys)
         dt = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "walker-evals/s", "cores":
+        # one walker-eval covers every box of the workload: scale a partial sample up by box count
+        per_eval = dt * len(hs) / len(sample)
+        result["cpu_baseline"] = {"value": round(1.0 / per_eval, 6), "unit": "walker-evals/s", "cores":
                                   oracle.FFT_WORKERS, "kind": "oracle",
-                                  "sample": f"1 walker (the batch's first) x {len(hs)} boxes ({wl.boxes[0].n}^3, "
-                                            f"{'/'.join(str(n) for n in nrad)} radii) in {dt:.2f} s",
+                                  "sample": f"1 walker (the batch's first) x {len(sample)} of {len(hs)} boxes "
+                                            f"({wl.boxes[0].n}^3, {'/'.join(str(n) for n in nrad)} radii) in "
+                                            f"{dt:.2f} s" + ("" if len(sample) == len(hs) else
+                                                             f", scaled by {len(hs)}/{len(sample)} boxes"),
                                   "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+    b.close()
+
+    if not args.no_velocity:
+        # the same step with the velocity-gradient factor H / (dv_r/dr + H) in dT_b
+        log("timing the variant with the velocity-gradient factor")
+        vb = Batch(xs, torch, wl, amp, walkers, phys_kw={"velocity": 1})
+        ms_v = vb.timed(vb.step, args.steps, warmup=args.warmup)
+        result["velocity_term"] = {"ms_per_step": round(ms_v, 4), "walker_evals_per_s": round(nw / (ms_v * 1e-3), 2),
+                                   "note": "same step with dT_b times H / (dv_r/dr + H), |dv_r/dr| / H <= 0.2"}
+        vb.close()
+
+    if not args.no_scaling:
+        log("HBM probes")
+        probes = hbm_probes(xs, torch)
+        result["hbm_probes"] = probes
+        for k in ("ion", "axis_fwd", "axis_bins"):
+            if k in result["kernels"]:
+                result["kernels"][k]["frac_of_copy_probe"] = round(result["kernels"][k]["GBps"] /
+                                                                   probes["copy"]["GBps"], 4)
+
+    if not args.no_configs and args.workload == "batched-256":
+        log("plain workloads (64^3 FP64, 128^3 x 3 z FP32) with the oracle beside them")
+        result["plain_configs"] = section_plain_configs(xs, torch, amp, max(2, args.steps // 2))
+        log("uneven BF16 workload (128^3 / 256^3 x 3 z, 256 walkers)")
+        result["uneven_mix"] = section_workload(xs, torch, amp, "uneven-mix", max(2, args.steps // 3))
+        log("large workload (512^3 x 3 z, 1024 walkers)")
+        result["large_512"] = section_workload(xs, torch, amp, "large-512", 1)
+
     props = torch.cuda.get_device_properties(0)
     result["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
                         "compute_units": props.multi_processor_count,
                         "lds_per_block_bytes": props.shared_memory_per_block,
                         "l2_bytes": getattr(props, "L2_cache_size", None),
                         "memory_gib": round(props.total_memory / 2 ** 30, 1)}
-    ctx.close()
-    if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copy of 1 GiB done")
+    if args.calibrate:
+        c = xs.Context(0, phys=xs.physics())
+        for kind in ("read", "write", "copy", "tile"):
+            c.probe_bandwidth(kind, (3800 << 20) + (64 << 10), reps=1)
+        c.close()
+        log("calibration probes done")
     print(json.dumps(result), flush=True)
 
 

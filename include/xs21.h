@@ -208,10 +208,25 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
                       double* pk, double* k_mean, double* counts, double* xhi_mean);
 
 /* Batched-path fields of one walker on one box, from the resident smoothed
- * boxes (same kernels as xs21_eval_batch).  x_hi and dtb are DEVICE arrays of
- * n^3 values of the box dtype; either may be NULL.  Asynchronous. */
+ * boxes: the ionisation kernel of xs21_eval_batch runs over a group of this
+ * one walker and writes the per-cell x_HI (Section 2.1, eq. 1 and the partial
+ * ionisation at the cell radius) and dT_b (eq. 4) it transforms.  x_hi and
+ * dtb are DEVICE arrays of n^3 values of the box dtype, both required.  Uses
+ * the evaluation scratch of the workspace.  Asynchronous. */
 xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker,
                              void* x_hi, void* dtb);
+
+/* xs21_eval_batch (same arguments, outputs and errors), and in the same
+ * launches the x_HI and dT_b boxes of walker `field_walker` (an index into
+ * walkers) on boxes[field_box] (an index into boxes): the ionisation launch
+ * of that walker's group on that box also stores the per-cell values it
+ * transforms.  x_hi and dtb: DEVICE, n^3 values of the box dtype each.  For
+ * checking the batched kernel's per-cell output in its production launch
+ * shape.  EINVAL: index out of range or a NULL field output. */
+xs21_status xs21_eval_batch_fields(xs21_ctx* ctx, const xs21_box* boxes, int nb,
+                                   const xs21_walker* walkers, int nw, double* pk,
+                                   double* xhi_mean, int field_walker, int field_box,
+                                   void* x_hi, void* dtb);
 
 /* xs21_eval_batch for two-population walkers (Section 4, eq. 9).  The
  * criterion of eq. (1) weighs each collapsed halo by its own efficiency:
@@ -241,6 +256,15 @@ xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out);
  * evaluation.  field: DEVICE, n^3 values of the box dtype.  pk: HOST, n_bins
  * doubles.  Synchronous. */
 xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk);
+
+/* y[i] = erfc(x[i]) for i < n by the single-precision complementary error
+ * function the FP32 ionisation pass uses for the collapsed fraction of
+ * Section 2.1 (f_coll = erfc((delta_c - delta_R) / sqrt(2 (S_min - S_R)))):
+ * a degree-9 Chebyshev fit of erfc(z) exp(z^2) (Numerical Recipes, 2nd ed.,
+ * section 6.2, fractional error below 1.2e-7) with the hardware's approximate
+ * reciprocal and exponential.  x, y: DEVICE, n floats each.  Works on any
+ * context, prepared or not.  Asynchronous. */
+xs21_status xs21_erfc_f32(xs21_ctx* ctx, const float* x, float* y, long n);
 
 /* Likelihood epilogue (Section 2.5; redshifts combined as in Section 3.4).
  * Sets the mock observation of `box`: delta2_mock[b] is the mock
@@ -328,6 +352,20 @@ xs21_status xs21_profile(xs21_ctx* ctx, int enable);
  * be NULL. */
 xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long long* launches, double* bytes,
                               double* ops);
+
+/* HBM bandwidth probe: the practical ceiling beside the 8 TB/s peak for the
+ * path's memory-bound passes.  kind 0: read every 16-byte vector of the
+ * buffer once; 1: write it; 2: copy the first half to the second; 3: read it
+ * as 256^3 FP32 half spectra (rows padded to 144 complex values) in strided
+ * 128-byte segments over all z planes, the access pattern of the binning
+ * pass.  buf: DEVICE, `bytes` >= 1 MiB plus 32 KiB (kind 3: at least one
+ * spectrum of 75.5 MB plus 32 KiB), 256-byte aligned, contents overwritten;
+ * its last 32 KiB hold the read kernels' block sums.  One untimed launch,
+ * then `reps` launches timed with HIP events on the context stream.
+ * *gbps: bytes read plus written per second (1e9); *bytes_per_launch (may be
+ * NULL): those bytes for one launch.  Synchronous. */
+xs21_status xs21_probe_bandwidth(xs21_ctx* ctx, int kind, void* buf, size_t bytes, int reps,
+                                 double* gbps, double* bytes_per_launch);
 
 /* ---------------------------------------------------------------- host planning */
 /* Pure host functions (no device, no context): the FP64 scalar planning the

@@ -223,6 +223,26 @@ def smooth(delta_hat: np.ndarray, n: int, box: float, radius: float) -> np.ndarr
                             workers=FFT_WORKERS)
 
 
+def _elementwise(fn, x: np.ndarray) -> np.ndarray:
+    """fn applied to every element of x, in contiguous chunks on FFT_WORKERS
+    threads (NumPy/SciPy ufuncs release the GIL).  Each element is computed on
+    its own, so the result does not depend on the split."""
+    flat = np.ascontiguousarray(x).reshape(-1)
+    out = np.empty_like(flat)
+    if FFT_WORKERS <= 1 or flat.size < (1 << 20):
+        out[:] = fn(flat)
+        return out.reshape(x.shape)
+    from concurrent.futures import ThreadPoolExecutor
+    edges = np.linspace(0, flat.size, FFT_WORKERS + 1).astype(np.int64)
+
+    def run(i):
+        out[edges[i]:edges[i + 1]] = fn(flat[edges[i]:edges[i + 1]])
+
+    with ThreadPoolExecutor(max_workers=FFT_WORKERS) as ex:
+        list(ex.map(run, range(FFT_WORKERS)))
+    return out.reshape(x.shape)
+
+
 def collapse_fraction(delta_r: np.ndarray, dsig2: float, delta_c: float) -> np.ndarray:
     """Conditional collapse fraction erfc((delta_c - delta_R) / sqrt(2 (S_min - S_R))).
 
@@ -232,7 +252,8 @@ def collapse_fraction(delta_r: np.ndarray, dsig2: float, delta_c: float) -> np.n
     """
     if dsig2 <= 0.0:
         return np.zeros_like(delta_r)
-    return scipy.special.erfc((delta_c - delta_r) / math.sqrt(2.0 * dsig2))
+    scale = math.sqrt(2.0 * dsig2)
+    return _elementwise(lambda v: scipy.special.erfc((delta_c - v) / scale), delta_r)
 
 
 def ionization_field(delta: np.ndarray, box: float, z: float, zeta: float, t_vir: float,

@@ -86,12 +86,16 @@ _SIGNATURES = {
     "xs21_eval": (_I, [_P, _I, ctypes.POINTER(Walker), _DP, _I, _P, _P, _DP, _DP, _DP, _DP]),
     "xs21_materialize": (_I, [_P, _I, ctypes.POINTER(Walker), _P, _P]),
     "xs21_eval_batch2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker2), _I, _P, _P]),
+    "xs21_eval_batch_fields": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Walker), _I, _P, _P, _I,
+                                    _I, _P, _P]),
     "xs21_mcmc_lnprob": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Sampler), _P, _I, _P]),
     "xs21_mcmc_step": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(Sampler), _P, _P, _I, _P, _P]),
     "xs21_materialize2": (_I, [_P, _I, ctypes.POINTER(Walker2), _P, _P]),
     "xs21_smoothed": (_I, [_P, _I, _I, _P]),
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
     "xs21_resmooth": (_I, [_P, _I, _P]),
+    "xs21_erfc_f32": (_I, [_P, _P, _P, ctypes.c_long]),
+    "xs21_probe_bandwidth": (_I, [_P, _I, _P, ctypes.c_size_t, _I, _DP, _DP]),
     "xs21_set_mock": (_I, [_P, _I, _DP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "xs21_chi2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P]),
     "xs21_profile": (_I, [_P, _I]),
@@ -266,6 +270,28 @@ class Context:
         """Batched evaluation; returns device tensors pk [nw, nb, nbmax] and xhi [nw, nb] (float64)."""
         return self._batch(boxes, walkers, pk, xhi, Walker, library().xs21_eval_batch)
 
+    def eval_batch_fields(self, boxes: Sequence[int], walkers, field_walker: int, field_box: int, pk=None,
+                          xhi=None):
+        """eval_batch that also returns the x_HI and dT_b boxes of walkers[field_walker] on
+        boxes[field_box], written by that walker's batched ionisation launch."""
+        torch = self.torch
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        warr, nw = _walkers_array(walkers, Walker)
+        nbmax = max(self.boxes[b]["n_bins"] for b in boxes)
+        if pk is None:
+            pk = torch.empty((nw, len(boxes), nbmax), dtype=torch.float64, device=self.device)
+        if xhi is None:
+            xhi = torch.empty((nw, len(boxes)), dtype=torch.float64, device=self.device)
+        b = self.boxes[boxes[field_box]] if 0 <= field_box < len(boxes) else self.boxes[boxes[0]]
+        n = b["n"]
+        td = torch.float64 if b["dtype"] == F64 else torch.float32
+        fx = torch.empty((n, n, n), dtype=td, device=self.device)
+        fd = torch.empty((n, n, n), dtype=td, device=self.device)
+        _check(library().xs21_eval_batch_fields(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()),
+                                                ctypes.c_void_p(xhi.data_ptr()), int(field_walker), int(field_box),
+                                                ctypes.c_void_p(fx.data_ptr()), ctypes.c_void_p(fd.data_ptr())))
+        return pk, xhi, fx, fd
+
     def eval_batch2(self, boxes: Sequence[int], walkers, pk=None, xhi=None):
         """eval_batch for two-population walkers (zeta0, R_mfp, T_feed, alpha, beta), eq. (9)."""
         return self._batch(boxes, walkers, pk, xhi, Walker2, library().xs21_eval_batch2)
@@ -370,6 +396,28 @@ class Context:
         f = field.contiguous()
         _check(library().xs21_power_spectrum(self._ctx, box, ctypes.c_void_p(f.data_ptr()), _dptr(pk)))
         return pk
+
+    def probe_bandwidth(self, kind: str, nbytes: int = 1 << 30, reps: int = 5) -> dict:
+        """HBM probe ("read", "write", "copy", "tile"): GB/s of bytes read + written per launch."""
+        k = {"read": 0, "write": 1, "copy": 2, "tile": 3}[kind]
+        buf = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        g = ctypes.c_double()
+        m = ctypes.c_double()
+        _check(library().xs21_probe_bandwidth(self._ctx, k, ctypes.c_void_p(buf.data_ptr() + off), nbytes, reps,
+                                              ctypes.byref(g), ctypes.byref(m)))
+        del buf
+        return {"GBps": g.value, "bytes_per_launch": m.value}
+
+    def erfc_f32(self, x):
+        """erfc of a float32 device tensor by the FP32 routine of the ionisation pass."""
+        t = x.contiguous()
+        if t.dtype != self.torch.float32 or not t.is_cuda:
+            raise ValueError("erfc_f32 needs a float32 device tensor")
+        y = self.torch.empty_like(t)
+        _check(library().xs21_erfc_f32(self._ctx, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                       t.numel()))
+        return y
 
     def set_mock(self, box: int, delta2_mock, noise_sigma=None, model_err=0.25, k_lo=0.15, k_hi=1.0):
         """Mock Delta^2 (and optional noise) of `box` for the chi^2 epilogue; host arrays of n_bins."""

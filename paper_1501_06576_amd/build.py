@@ -8,12 +8,14 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxs21.so")
-SOURCES = ["kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "api.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "api.cpp",
+           "plan.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
@@ -28,11 +30,11 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles every source for gfx950 and links libxs21.so next to this file."""
-    objs = []
+    """Compiles every source for gfx950 (in parallel) and links libxs21.so next to this file."""
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(build_dir, src + ".o")
         cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -40,7 +42,11 @@ def build(verbose: bool = False) -> str:
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr}")
-        objs.append(obj)
+        return obj
+
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -62,12 +62,15 @@ struct BoxRec {
   std::vector<long> live_off; // first entry of radius j in live (nr + 1 offsets)
   std::vector<int32_t> live_y;   // smoothing y pass: (radius << 24) | tile of the kx tiles up to each kmax
   std::vector<long> live_y_off;  // first entry of radius j in live_y
+  std::vector<int32_t> bins_live;   // binning pass: tiles with a column inside ny^2 + kx^2 <= (n/2)^2
+  double live_yx = 0;            // (ky, kx < n/2) pairs inside that disk
   bool mock_set = false;      // xs21_set_mock has uploaded the likelihood table
   // workspace offsets
   size_t off_bintab = 0, off_counts = 0, off_cut = 0, off_delta = 0, off_od = 0, off_dR = 0, off_like = 0;
   size_t off_slots = 0;       // SlotPlan2 per radius slot, for planning from device walker parameters
   size_t off_live = 0;        // the live-tile list of the smoothing z pass
   size_t off_live_y = 0;      // the live-tile list of the smoothing y pass
+  size_t off_bins_live = 0;   // the live-tile list of the binning pass
   xs21::BoxPlan bplan{};      // the box's planning scalars (kernel argument)
 
   size_t cells() const { return static_cast<size_t>(n) * n * n; }
@@ -118,6 +121,7 @@ struct Layout {
   size_t one_table = 0, one_table_bytes = 0;  // single-walker table
   size_t outs = 0;                          // small device outputs (plain / debug)
   size_t samp = 0, samp_pk = 0;             // sampler: proposals, aux, chi^2; their P(k)
+  size_t slot_tab = 0;                      // sorted flag-test tables of one walker group
   size_t scratch = 0, scratch_bytes = 0;    // union of smoothing / evaluation / plain scratch
   size_t total = 0;
 };
@@ -283,6 +287,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
     off += align_up(b.live.size() * sizeof(int32_t));
     b.off_live_y = off;
     off += align_up(b.live_y.size() * sizeof(int32_t));
+    b.off_bins_live = off;
+    off += align_up(b.bins_live.size() * sizeof(int32_t));
     b.off_like = off;
     off += align_up(3 * static_cast<size_t>(b.nbins) * 8);
     b.off_slots = off;
@@ -315,6 +321,8 @@ Layout compute_layout(const xs21_ctx* c, int storage, int max_walkers, int max_p
   off += align_up(static_cast<size_t>(max_walkers) * 8 * 8);
   L.samp_pk = off;
   off += align_up(static_cast<size_t>(max_walkers) * boxes.size() * xs21::max_bins() * 8);
+  L.slot_tab = off;
+  off += align_up(xs21::slot_table_bytes());
   L.scratch = off;
   L.scratch_bytes = scratch;
   off += align_up(scratch);
@@ -554,9 +562,11 @@ EvalSlot eval_slot(const BoxRec& b, unsigned char* base, int count) {
 }
 
 // Ionisation + dT_b + x pass for `count` walkers whose tables are at wc/thr
-// (the ALU-bound stage), on stream st.
+// (the ALU-bound stage), on stream st.  field_walker >= 0: that walker of the
+// group also writes its x_HI and dT_b boxes to fx / fd (device).
 hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlot& sl, const void* dR, int storage,
-                     int nr, const void* wc, const void* thr, const void* zt, int count, double radii_used) {
+                     int nr, const void* wc, const void* thr, const void* zt, int count, double radii_used,
+                     int field_walker = -1, void* fx = nullptr, void* fd = nullptr) {
   const long n = b.n, h = static_cast<long>(b.half());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
@@ -569,7 +579,8 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
       c, st, XS21_K_ION, nr * cells * store_size(storage) + cells * rs + count * modes * 2 * rs,
       [&] {
         return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_od, nr, wc, thr, zt, count, tb,
-                                c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st);
+                                c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st,
+                                field_walker, fx, fd, c->ws + c->lay.slot_tab);
       },
       ion_ops);
 }
@@ -584,20 +595,24 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
   const long parts = xs21::bins_parts(b.n, count);
   const void* tw = tw_ptr(c, b.dtype);
-  // y pass of the kx < N/2 columns, then of the Nyquist planes
-  hipError_t e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * n * n * (n / 2) * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, count * n, hp, n / 2, nullptr, 1, 0, 0, tw,
-                             kNtab, st);
+  // y pass of the kx < N/2 columns, then of the Nyquist planes; only modes
+  // with ny^2 + kx^2 <= (N/2)^2 are stored (no other mode is binned)
+  const double ntl = static_cast<double>(b.bins_live.size());
+  hipError_t e = timed(c, st, XS21_K_AXIS_FWD, count * n * (n * (n / 2) + b.live_yx) * 2 * rs, [&] {
+    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, count * n, hp, n / 2, false, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, st, XS21_K_AXIS_FWD, 2 * count * n * n * 2 * rs, [&] {
-    return xs21::launch_axis(b.dtype, b.n, -1, 0, sl.nyq, sl.nyq, count, n, n, nullptr, 1, 0, 0, tw, kNtab, st);
+  e = timed(c, st, XS21_K_AXIS_FWD, count * n * (n + 1) * 2 * rs, [&] {
+    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, count, n, n, true, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
-  e = timed(c, st, XS21_K_AXIS_BINS, count * modes * 2 * rs, [&] {
+  // the binning pass reads the live tiles (TI columns x N values each)
+  e = timed(c, st, XS21_K_AXIS_BINS, count * ntl * xs21::axis_tile_cols(b.n) * n * 2 * rs, [&] {
     return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, count, parts,
-                                  reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.nbins, sl.part, tw, kNtab,
-                                  st);
+                                  reinterpret_cast<const int32_t*>(c->ws + b.off_bins_live),
+                                  static_cast<long>(b.bins_live.size()),
+                                  reinterpret_cast<const int8_t*>(c->ws + b.off_bintab), b.bintab.data(), b.nbins,
+                                  sl.part, tw, kNtab, st);
   });
   if (e != hipSuccess) return e;
   const double L3 = b.box * b.box * b.box;
@@ -741,6 +756,12 @@ xs21_status xs21_add_box(xs21_ctx* ctx, const void* delta, int on_device, xs21_d
       b.live_y_off.push_back(static_cast<long>(b.live_y.size()));
     }
   }
+  b.bins_live = xs21::bins_live_tiles(n);
+  for (long kx = 0; kx < n / 2; ++kx)
+    for (long ky = 0; ky < n; ++ky) {
+      const long ny = ky < n / 2 ? ky : ky - n;
+      b.live_yx += (ny * ny + kx * kx <= static_cast<long>(n / 2) * (n / 2)) ? 1.0 : 0.0;
+    }
   b.bintab = xs21::plan::bins(n, n_bins);
   xs21::plan::bin_stats(n, n_bins, box_mpc, b.bintab, b.counts, b.kmean);
   if (on_device) {
@@ -842,6 +863,8 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
                                  hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_live_y, b.live_y.data(), b.live_y.size() * sizeof(int32_t),
                                  hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws + b.off_bins_live, b.bins_live.data(),
+                                 b.bins_live.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     {
       const auto slots = xs21::plan::slots2(ctx->phys, b.z, b.radii);
       b.bplan = xs21::plan::box_plan(ctx->phys, b.z, b.nr());
@@ -872,8 +895,11 @@ namespace {
 
 // Shared body of xs21_eval_batch (w1) and xs21_eval_batch2 (w2): exactly
 // one walker array is non-null.
+// field_walker >= 0: the ionisation launch of that walker on boxes[field_box]
+// also writes its x_HI and dT_b boxes to fx / fd.
 xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* w1,
-                            const xs21_walker2* w2, int nw, double* pk, double* xhi_mean) {
+                            const xs21_walker2* w2, int nw, double* pk, double* xhi_mean, int field_walker = -1,
+                            int field_box = -1, void* fx = nullptr, void* fd = nullptr) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
@@ -891,6 +917,8 @@ xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
   for (int w = 0; w < nw; ++w)
     if (w1 ? !xs21::plan::valid_walker(w1[w]) : !xs21::plan::valid_walker2(w2[w]))
       return fail(XS21_EINVAL, "walker %d has invalid parameters", w);
+  if (field_walker >= 0 && (field_walker >= nw || field_box < 0 || field_box >= nb || !fx || !fd))
+    return fail(XS21_EINVAL, "field walker / box out of range or null field output");
   auto r_mfp = [&](long w) { return w1 ? w1[w].r_mfp : w2[w].r_mfp; };
 
   const hipStream_t st = ctx->stream;
@@ -948,9 +976,11 @@ xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
         double* pk_out = pk ? pk + (wg * nb + i) * nbmax : nullptr;
         double* xh_out = xhi_mean ? xhi_mean + wg * nb + i : nullptr;
         const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, g);
+        const int fw = (i == field_box && field_walker >= wg && field_walker < wg + g) ? field_walker - wg : -1;
         HIPCHECK(ctx, ion_stage(ctx, st, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc + g0 * b.wc_size(),
                                 thr + static_cast<size_t>(g0) * thr_w,
-                                zt ? zt + static_cast<size_t>(g0) * xs21::kZetaPitch * rs : nullptr, g, used));
+                                zt ? zt + static_cast<size_t>(g0) * xs21::kZetaPitch * rs : nullptr, g, used, fw, fx,
+                                fd));
         HIPCHECK(ctx, mem_stage(ctx, st, b, sl, g, pk_out, static_cast<long>(nb) * nbmax, nbmax, xh_out, nb));
       }
     }
@@ -972,6 +1002,14 @@ xs21_status xs21_eval_batch2(xs21_ctx* ctx, const xs21_box* boxes, int nb, const
                              double* pk, double* xhi_mean) {
   if (!walkers) return fail(XS21_EINVAL, "null walkers");
   return eval_batch_impl(ctx, boxes, nb, nullptr, walkers, nw, pk, xhi_mean);
+}
+
+xs21_status xs21_eval_batch_fields(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers, int nw,
+                                   double* pk, double* xhi_mean, int field_walker, int field_box, void* x_hi,
+                                   void* dtb) {
+  if (!walkers) return fail(XS21_EINVAL, "null walkers");
+  if (field_walker < 0) return fail(XS21_EINVAL, "field_walker must be >= 0");
+  return eval_batch_impl(ctx, boxes, nb, walkers, nullptr, nw, pk, xhi_mean, field_walker, field_box, x_hi, dtb);
 }
 
 }  // extern "C"
@@ -1182,26 +1220,22 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
                                dR + static_cast<size_t>(j) * b.cells() * real_size(b.dtype)));
   const unsigned char* thr = wc + align_up(b.wc_size());
 
-  // the eval scratch of a plain call sits after the plain smoothed boxes
+  // the eval scratch of a plain call sits after the plain smoothed boxes; the
+  // fields (when asked for) come from the same ionisation launch, staged in
+  // the hat / tmp area, which the smoothing no longer needs
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   const EvalSlot sl = eval_slot(b, eval_area, 1);
-  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, dR, b.dtype, nr, wc, thr, nullptr, 1, nr));
+  const size_t fbytes = b.cells() * real_size(b.dtype);
+  if ((x_hi || dtb) && 2 * align_up(fbytes) > 2 * align_up(b.spec_bytes()))
+    return fail(XS21_EUNSUPPORTED, "field staging does not fit");
+  void* fx = hat;
+  void* fd = hat + align_up(fbytes);
+  const bool fields = x_hi || dtb;
+  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, dR, b.dtype, nr, wc, thr, nullptr, 1, nr, fields ? 0 : -1,
+                          fields ? fx : nullptr, fields ? fd : nullptr));
   HIPCHECK(ctx, mem_stage(ctx, ctx->stream, b, sl, 1, outs, b.nbins, b.nbins, outs + 128, 1));
-  if (x_hi || dtb) {
-    // fields through the same per-cell arithmetic; staged in the hat/tmp area
-    const size_t fbytes = b.cells() * real_size(b.dtype);
-    if (2 * align_up(fbytes) > 2 * align_up(b.spec_bytes()))
-      return fail(XS21_EUNSUPPORTED, "field staging does not fit");
-    void* fx = hat;
-    void* fd = hat + align_up(fbytes);
-    const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
-    HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-      return xs21::launch_materialize(b.dtype, b.dtype, b.n, dR, ctx->ws + b.off_od, nr, wc, thr, nullptr, tbv,
-                                      ctx->phys.delta_c, fx, fd, ctx->stream);
-    }));
-    if (x_hi) HIPCHECK(ctx, hipMemcpyAsync(x_hi, fx, fbytes, hipMemcpyDeviceToHost, ctx->stream));
-    if (dtb) HIPCHECK(ctx, hipMemcpyAsync(dtb, fd, fbytes, hipMemcpyDeviceToHost, ctx->stream));
-  }
+  if (x_hi) HIPCHECK(ctx, hipMemcpyAsync(x_hi, fx, fbytes, hipMemcpyDeviceToHost, ctx->stream));
+  if (dtb) HIPCHECK(ctx, hipMemcpyAsync(dtb, fd, fbytes, hipMemcpyDeviceToHost, ctx->stream));
   double host_out[129];
   HIPCHECK(ctx, hipMemcpyAsync(host_out, outs, 129 * 8, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1219,6 +1253,7 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!walker || !xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  if (!x_hi || !dtb) return fail(XS21_EINVAL, "null field output");
   const BoxRec& b = ctx->boxes[box];
   if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
   build_tables(ctx->phys, b, walker, 1, false, b.radii, static_cast<unsigned char*>(ctx->pinned), 1);
@@ -1227,12 +1262,10 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
   HIPCHECK(ctx, hipMemcpyAsync(wc, ctx->pinned, tb_bytes, hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
   ctx->upload_pending = true;
-  const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
-  HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_od, b.nr(), wc,
-                                    wc + align_up(b.wc_size()), nullptr, tbv, ctx->phys.delta_c, x_hi, dtb,
-                                    ctx->stream);
-  }));
+  // the batched ionisation kernel over a group of this one walker, writing its fields
+  const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, 1);
+  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc,
+                          wc + align_up(b.wc_size()), nullptr, 1, -1.0, 0, x_hi, dtb));
   return XS21_OK;
 }
 
@@ -1242,6 +1275,7 @@ xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* w
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!walker || !xs21::plan::valid_walker2(*walker)) return fail(XS21_EINVAL, "invalid walker");
+  if (!x_hi || !dtb) return fail(XS21_EINVAL, "null field output");
   const BoxRec& b = ctx->boxes[box];
   if (ctx->upload_pending) HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
   build_tables2(ctx->phys, b, walker, 1, static_cast<unsigned char*>(ctx->pinned), 1);
@@ -1256,12 +1290,9 @@ xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* w
                               base + t.thr, xs21::thr_stride(), base + t.zt, xs21::kZetaPitch, ctx->phys.delta_c,
                               ctx->stream);
   }));
-  const double tbv = ctx->phys.tb0_mK * std::sqrt((1.0 + b.z) / 10.0);
-  HIPCHECK(ctx, timed(ctx, ctx->stream, XS21_K_OTHER, 0.0, [&] {
-    return xs21::launch_materialize(b.dtype, b.storage, b.n, ctx->ws + b.off_dR, ctx->ws + b.off_od, b.nr(),
-                                    base + t.wc, base + t.thr, base + t.zt, tbv, ctx->phys.delta_c, x_hi, dtb,
-                                    ctx->stream);
-  }));
+  const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, 1);
+  HIPCHECK(ctx, ion_stage(ctx, ctx->stream, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), base + t.wc,
+                          base + t.thr, base + t.zt, 1, -1.0, 0, x_hi, dtb));
   return XS21_OK;
 }
 
@@ -1293,13 +1324,13 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
   const void* tw = tw_ptr(ctx, b.dtype);
   HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, sl.spec, sl.nyq, n * n, tw, kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, sl.spec, sl.spec, n, hp, n / 2, nullptr, 1, 0, 0, tw, kNtab,
-                                  ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis(b.dtype, b.n, -1, 0, sl.nyq, sl.nyq, 1, n, n, nullptr, 1, 0, 0, tw, kNtab,
-                                  ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, n, hp, n / 2, false, tw, kNtab, ctx->stream));
+  HIPCHECK(ctx, xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, 1, n, n, true, tw, kNtab, ctx->stream));
   HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1, parts,
-                                       reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.nbins, part, tw,
-                                       kNtab, ctx->stream));
+                                       reinterpret_cast<const int32_t*>(ctx->ws + b.off_bins_live),
+                                       static_cast<long>(b.bins_live.size()),
+                                       reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.bintab.data(),
+                                       b.nbins, part, tw, kNtab, ctx->stream));
   const double L3 = b.box * b.box * b.box;
   HIPCHECK(ctx, xs21::launch_finalize(1, part, parts, b.nbins, nullptr, 0,
                                       reinterpret_cast<const double*>(ctx->ws + b.off_counts),
@@ -1307,6 +1338,43 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
                                       0, ctx->stream));
   HIPCHECK(ctx, hipMemcpyAsync(pk, outs, b.nbins * 8, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_probe_bandwidth(xs21_ctx* ctx, int kind, void* buf, size_t bytes, int reps, double* gbps,
+                                 double* bytes_per_launch) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (kind < 0 || kind > 3) return fail(XS21_EINVAL, "unknown probe kind %d", kind);
+  if (!buf || reps < 1 || !gbps) return fail(XS21_EINVAL, "null or empty argument");
+  if (reinterpret_cast<uintptr_t>(buf) % kAlign) return fail(XS21_EINVAL, "probe buffer not 256-byte aligned");
+  const size_t sink = align_up(xs21::probe_sink_bytes());
+  if (bytes < sink + (kind == 3 ? xs21::probe_tile_spectrum_bytes() : (1u << 20)))
+    return fail(XS21_EINVAL, "probe buffer of %zu bytes is too small", bytes);
+  const size_t body = (bytes - sink) / kAlign * kAlign;
+  float* sk = reinterpret_cast<float*>(static_cast<unsigned char*>(buf) + body);
+  double moved = 0.0;
+  hipEvent_t a = pooled_event(ctx), b = pooled_event(ctx);
+  if (!a || !b) return fail(XS21_EDEVICE, "event creation failed");
+  HIPCHECK(ctx, xs21::launch_probe(kind, buf, body, sk, &moved, ctx->stream));   // warm-up
+  HIPCHECK(ctx, hipEventRecord(a, ctx->stream));
+  for (int r = 0; r < reps; ++r) HIPCHECK(ctx, xs21::launch_probe(kind, buf, body, sk, &moved, ctx->stream));
+  HIPCHECK(ctx, hipEventRecord(b, ctx->stream));
+  HIPCHECK(ctx, hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHECK(ctx, hipEventElapsedTime(&ms, a, b));
+  ctx->pool.push_back(a);
+  ctx->pool.push_back(b);
+  *gbps = moved * reps / (static_cast<double>(ms) * 1e-3) / 1e9;
+  if (bytes_per_launch) *bytes_per_launch = moved;
+  return XS21_OK;
+}
+
+xs21_status xs21_erfc_f32(xs21_ctx* ctx, const float* x, float* y, long n) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!x || !y || n < 1) return fail(XS21_EINVAL, "null or empty argument");
+  HIPCHECK(ctx, xs21::launch_erfc(x, y, static_cast<size_t>(n), ctx->stream));
   return XS21_OK;
 }
 

@@ -18,8 +18,11 @@
 
 #include <stdint.h>
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -31,6 +34,16 @@ namespace xs21 {
 constexpr int kMaxGroup = 64;   // walkers per ionisation launch (x_HI sums in LDS)
 constexpr int kNrMax = 40;      // radii held in registers per cell
 constexpr int kMaxBins = 64;
+constexpr int kBinSlotTeams = 64;  // largest FFT team of the binning pass (N = 512)
+
+// Slot rows of the binning pass for one launch over bins [b0, b0 + nbc):
+// team index j keeps bins lo[j] .. b0 + nbc - 1 at rows base[j] ..; `rows`
+// rows in all (passed by value).
+struct BinSlots {
+  int16_t lo[kBinSlotTeams];
+  int16_t base[kBinSlotTeams];
+  int32_t rows;
+};
 
 // Row pitch of a half spectrum: N/2 + 1 complex values padded to a multiple of
 // 16 (128 bytes in FP32), so that strided passes read whole aligned lines.
@@ -355,7 +368,11 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis(const cplx<T>* src, c
 // block issues the global loads of its next tile into registers before the
 // FFT of the current one, so that memory latency overlaps the transform.
 // Loads and stores are streaming: each element is touched once per pass.
-template <typename T, int N, int DIR>
+// DISK (forward y pass of a spectrum that is only binned): outputs whose mode
+// has ny^2 + kx^2 > (N/2)^2 are never binned (|n| > N/2 for every nz), so
+// they are not stored.  DISK 1: kx is the column index (the kx < N/2 rows);
+// DISK 2: kx = N/2 for every column (the Nyquist plane, [ky][z]).
+template <typename T, int N, int DIR, int DISK = 0>
 __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* src, cplx<T>* dst, long inner,
                                                                 long tiles_x, long ntiles,
                                                                 const cplx<T>* __restrict__ tw, int tstride) {
@@ -390,8 +407,23 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
       for (int k = 0; k < L; ++k) pre[k] = load_stream(src + offn + static_cast<long>(k) * NSTEP * inner);
     }
     fft_team<N, DIR, T, typename A::Plan>(lds + c, A::TI, n0, twl, 1);
+    int kx2 = 0;
+    if constexpr (DISK == 1) {
+      const int kx = static_cast<int>((g % tiles_x) * A::TI) + c;
+      kx2 = kx * kx;
+    } else if constexpr (DISK == 2) {
+      kx2 = (N / 2) * (N / 2);
+    }
 #pragma unroll
-    for (int k = 0; k < L; ++k) store_stream(dst + off + static_cast<long>(k) * NSTEP * inner, lds[t + k * A::NT]);
+    for (int k = 0; k < L; ++k) {
+      bool keep = true;
+      if constexpr (DISK != 0) {
+        const int ky = n0 + k * NSTEP;
+        const int ny = ky < N / 2 ? ky : ky - N;
+        keep = ny * ny + kx2 <= (N / 2) * (N / 2);
+      }
+      if (keep) store_stream(dst + off + static_cast<long>(k) * NSTEP * inner, lds[t + k * A::NT]);
+    }
     __syncthreads();
   }
 }
@@ -404,10 +436,21 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 // one y (KM = the largest multiple of 16 <= N/2), "rest" tiles gather the
 // remaining columns (kx in [KM, N/2], the Nyquist plane for N >= 32) of 16
 // consecutive (y, kx) pairs.  Block i of a spectrum's `parts` blocks takes
-// tiles i, i + parts, i + 2 parts, ... (so that blocks running together read
-// neighbouring tiles), accumulates its bin sums over them and writes FP64
-// sums of w |X|^2 for bins [b0, b0 + nbc) to part[spectrum][i][nbins].
+// entries i, i + parts, i + 2 parts, ... of the list `tiles` (so that blocks
+// running together read neighbouring tiles), accumulates its bin sums over
+// them and writes FP64 sums of w |X|^2 for bins [b0, b0 + nbc) to
+// part[spectrum][i][nbins].  The list holds the tiles with at least one column
+// ny^2 + kx^2 <= (N/2)^2: no mode of the other columns is ever binned (the
+// y pass does not even store them).
 // Weights w: 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere (half spectrum).
+//
+// Every sum is FP64: |X|^2 of a mode is formed in T, each thread adds its
+// modes in double to running sums in LDS, and a fixed-order wave reduction
+// adds those.  A thread outputs the kz range [j M, j M + M) of its column, so
+// |n| >= min |nz| over that range and its modes never reach the bins below
+// BinSlots::lo[j]: it keeps double slots only for bins lo[j] .. b0 + nbc - 1,
+// at rows base[j] .. of a [rows][TI] slot array (same rows for every column
+// cc of a tile).
 // ---------------------------------------------------------------------------
 template <int N, int TI>
 struct BinTiles {
@@ -418,7 +461,7 @@ struct BinTiles {
   static constexpr long REST = (static_cast<long>(N) * RW + TI - 1) / TI;
   static constexpr long COUNT = MAIN + REST;
   // (ky, kx) of column cc of a tile, or ky = -1 past the end
-  __device__ static void column(long tile, int cc, int& ky, int& kx) {
+  __host__ __device__ static void column(long tile, int cc, int& ky, int& kx) {
     if constexpr (KM > 0) {
       if (tile < MAIN) {
         ky = static_cast<int>(tile / (KM / TI));
@@ -437,8 +480,9 @@ struct BinTiles {
 template <typename T, int N>
 __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src,
                                                                 const cplx<T>* __restrict__ nyq, long parts,
+                                                                const int32_t* __restrict__ tiles, long ntiles,
                                                                 const int8_t* __restrict__ bintab,
-                                                                int nbins, int b0, int nbc,
+                                                                int nbins, int b0, int nbc, BinSlots bs,
                                                                 double* __restrict__ part,
                                                                 const cplx<T>* __restrict__ tw, int tstride) {
   using A = AxisShape<N>;
@@ -449,18 +493,22 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
   constexpr int NW = A::NT / 64;                     // waves per block
   constexpr int L = N * A::TI / A::NT;               // loaded elements per thread and tile
   constexpr int NSTEP = A::NT / A::TI;
+  static_assert(A::TS <= kBinSlotTeams, "slot table too small for this team size");
   __shared__ cplx<T> lds[N * A::TI];
   __shared__ cplx<T> twl[N];
-  // slot[b][t]: thread t's running sum of bin b0 + b (nbc x NT values of T)
+  // slot[(base[j] + b - lo[j]) TI + cc]: running FP64 sum of bin b of the
+  // threads with team index j and column cc (bs.rows rows of TI values)
   HIP_DYNAMIC_SHARED(unsigned char, dyn_lds)
-  T* slot = reinterpret_cast<T*>(dyn_lds);
+  double* slot = reinterpret_cast<double*>(dyn_lds);
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int cc = t % A::TI, j = t / A::TI;  // loads: rows j + k NSTEP; FFT: team member j of column cc
   const long spec = blockIdx.x / parts, first = blockIdx.x % parts;
   const cplx<T>* sp = src + spec * N * PLANE;
   for (int m = t; m < N; m += A::NT) twl[m] = tw[m * tstride];
-  for (int b = 0; b < nbc; ++b) slot[b * A::NT + t] = T(0);  // own column only
+  for (int e = t; e < bs.rows * A::TI; e += A::NT) slot[e] = 0.0;
+  // this thread's slot of bin b0 + bb sits at slot[(brow + bb) TI + cc]
+  const int brow = bs.base[j] - (bs.lo[j] - b0);
   constexpr int NB2 = (N / 2) * (N / 2) + 1;  // |n|^2 > (N/2)^2 is never binned
   cplx<T> pre[L];
   const cplx<T>* nq = nyq + spec * N * N;
@@ -479,12 +527,14 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
       pre[k] = live ? v : cplx<T>{T(0), T(0)};
     }
   };
-  if (first < BT::COUNT) load(first);
-  for (long tile = first; tile < BT::COUNT; tile += parts) {
+  __syncthreads();  // slots cleared before any thread adds to them
+  if (first < ntiles) load(tiles[first]);
+  for (long e = first; e < ntiles; e += parts) {
+    const long tile = tiles[e];
 #pragma unroll
     for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
     __syncthreads();
-    if (tile + parts < BT::COUNT) load(tile + parts);
+    if (e + parts < ntiles) load(tiles[e + parts]);
     // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1.  Their
     // bins are loaded before the FFT, unconditionally (entry 0, the dropped DC
     // mode, stands in for modes that are not binned), so that the loads
@@ -503,32 +553,36 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
     }
     fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
     // |nz| is monotone along m, so equal bins come in runs, each added to the
-    // thread's own slot column once
+    // thread's own slot once
     const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
     int cur = -1;
-    T run = T(0);
+    double run = 0.0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const cplx<T> x = lds[(j * M + m) * A::TI + cc];
       const int b = bin[m] - b0;  // negative for modes that are not binned
       const int bb = (b >= 0 && b < nbc) ? b : -1;
       if (bb != cur) {
-        if (cur >= 0) slot[cur * A::NT + t] += run;
-        run = T(0);
+        if (cur >= 0) slot[(brow + cur) * A::TI + cc] += run;
+        run = 0.0;
         cur = bb;
       }
-      run += w * (x.x * x.x + x.y * x.y);
+      run += static_cast<double>(w * (x.x * x.x + x.y * x.y));
     }
-    if (cur >= 0) slot[cur * A::NT + t] += run;
+    if (cur >= 0) slot[(brow + cur) * A::TI + cc] += run;
     __syncthreads();  // the FFT buffer is read before the next tile is stored
   }
-  // one wave per bin sums the NT slot columns in a fixed order (deterministic)
+  // one wave per bin adds the slots of that bin over every (team index,
+  // column) in a fixed order (deterministic)
   double* out = part + (spec * parts + blockIdx.x % parts) * nbins + b0;
   for (int b = wave; b < nbc; b += NW) {
-    T sum = T(0);
-#pragma unroll
-    for (int i = 0; i < A::NT / 64; ++i) sum += slot[b * A::NT + i * 64 + lane];
-    const double d = wave_sum(static_cast<double>(sum));
+    double sum = 0.0;
+    for (int e = lane; e < A::TS * A::TI; e += 64) {
+      const int jj = e / A::TI, c = e % A::TI;
+      const int lo = bs.lo[jj] - b0;
+      if (b >= lo) sum += slot[(bs.base[jj] + b - lo) * A::TI + c];
+    }
+    const double d = wave_sum(sum);
     if (lane == 0) out[b] = d;
   }
 }
@@ -623,6 +677,132 @@ __device__ __forceinline__ void load_radii(const S* __restrict__ dR, size_t n3, 
   for (int s = 0; s < NR; ++s) d[s] = load_as<T>(dR, static_cast<size_t>(s < nr ? nr - 1 - s : 0) * n3 + cell);
 }
 
+// ---------------------------------------------------------------------------
+// Sorted-threshold flag test.  For one walker group (<= 64 walkers) and one
+// radius slot s, the set of walkers whose flag test ionises a cell is a
+// function of delta_R alone: walker w is in it iff thr[w][s] <= delta_R.  With
+// the group's thresholds of slot s sorted, S_0 <= ... <= S_63 (+inf for absent
+// walkers and unused slots), that set is the first k of them, k = #{j : S_j <=
+// delta_R}, i.e. the bits of the prefix mask P_s[k] (walkers of sorted positions
+// < k).  A cell is flagged for walker w iff bit w of OR_s P_s[k_s] is set: the
+// same compares as the per-walker test (ties included), reached by one binary
+// search per slot for the whole group instead of one compare per walker.
+// Per slot the table holds E_s[64]: S_0..S_62 in breadth-first (Eytzinger)
+// order of a complete 6-level search tree (node i has children 2i+1, 2i+2),
+// then S_63; and P_s[0..64] (rows of kMaskPitch).
+// ---------------------------------------------------------------------------
+constexpr int kSortWidth = 64;   // walkers per sorted group (= kMaxGroup)
+constexpr int kMaskPitch = 66;   // prefix masks per slot (65 used), 16-byte rows
+static_assert(kSortWidth == kMaxGroup, "one sorted table covers one walker group");
+
+// Tables of slots [0, gridDim.x) for walkers [0, nw) with thresholds
+// thr[w][kNrMax] (slot index as in the ionisation pass).  One block of 64
+// threads per slot; thread w ranks walker w's threshold (ties by index).
+template <typename T>
+__global__ __launch_bounds__(kSortWidth) void k_slot_tables(const T* __restrict__ thr, int nw, T* __restrict__ E,
+                                                            uint64_t* __restrict__ P) {
+  const int s = blockIdx.x, w = threadIdx.x;
+  __shared__ T v[kSortWidth];
+  __shared__ T srt[kSortWidth];
+  __shared__ int id[kSortWidth];
+  const T mine = w < nw ? thr[static_cast<size_t>(w) * kNrMax + s] : static_cast<T>(INFINITY);
+  v[w] = mine;
+  __syncthreads();
+  int r = 0;
+  for (int j = 0; j < kSortWidth; ++j) {
+    const T o = v[j];
+    r += (o < mine || (o == mine && j < w)) ? 1 : 0;
+  }
+  srt[r] = mine;
+  id[r] = w;
+  __syncthreads();
+  if (w < kSortWidth - 1) {
+    // node w of the search tree: level l, position p within the level; its
+    // in-order index (the sorted position it splits at) is (2p + 1) 2^(5 - l) - 1
+    const int l = 31 - __builtin_clz(static_cast<unsigned>(w + 1));
+    const int pos = w + 1 - (1 << l);
+    E[s * kSortWidth + w] = srt[((2 * pos + 1) << (5 - l)) - 1];
+  } else {
+    E[s * kSortWidth + w] = srt[kSortWidth - 1];
+  }
+  uint64_t m = 0;
+  for (int j = 0; j < w; ++j) m |= 1ull << id[j];
+  P[s * kMaskPitch + w] = m;
+  if (w == kSortWidth - 1) P[s * kMaskPitch + kSortWidth] = m | (1ull << id[w]);
+}
+
+// Walker mask of one cell from the sorted tables: E (in LDS) and P (global),
+// for every one of the kNrMax slots.  The cell's delta_R are loaded four
+// slots at a time, one group ahead; slots past the ladder hold only +inf
+// thresholds and re-read the cell radius's value (a cache hit) instead of
+// branching, since a branch would force the pending loads to complete early.
+// The four searches of a group run level by level, so their LDS reads issue
+// together, and the mask reads of a group are consumed only after the next
+// group's searches.  Returns bits 0..31 in lo and 32..63 in hi.
+template <typename T, typename S>
+__device__ __forceinline__ void sorted_flags(const S* __restrict__ dR, size_t n3, size_t cell, int nr, const T* E,
+                                             const uint64_t* __restrict__ P, uint32_t& lo, uint32_t& hi) {
+  constexpr int GS = 4, NG = kNrMax / GS;
+  static_assert(kNrMax % GS == 0, "slots come in groups of 4");
+  const auto ld = [&](int s) {
+    return load_as<T>(dR, static_cast<size_t>(nr - 1 - (s < nr ? s : 0)) * n3 + cell);
+  };
+  T dn[GS];
+#pragma unroll
+  for (int j = 0; j < GS; ++j) dn[j] = ld(j);
+  uint64_t acc = 0, pend[GS] = {0, 0, 0, 0};
+  // a rolled loop: unrolled, the compiler keeps every slot's base address live
+  // across the cell loop (and spills them)
+#pragma unroll 1
+  for (int g = 0; g < NG; ++g) {
+    T dv[GS];
+#pragma unroll
+    for (int j = 0; j < GS; ++j) dv[j] = dn[j];
+    const int gn = g + 1 < NG ? g + 1 : g;   // the last group re-reads itself (cache hits)
+#pragma unroll
+    for (int j = 0; j < GS; ++j) dn[j] = ld(gn * GS + j);
+    // the search walks byte offsets a = sizeof(T) i of node i within the
+    // slot's tree: child 2i + 1 + b is at 2a + sizeof(T) (1 + b)
+    const unsigned char* eb = reinterpret_cast<const unsigned char*>(E + g * GS * kSortWidth);
+    int a[GS];
+#pragma unroll
+    for (int j = 0; j < GS; ++j) a[j] = 0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      T e[GS];
+#pragma unroll
+      for (int j = 0; j < GS; ++j) e[j] = *reinterpret_cast<const T*>(eb + j * kSortWidth * sizeof(T) + a[j]);
+#pragma unroll
+      for (int j = 0; j < GS; ++j)
+        a[j] = 2 * a[j] + (e[j] <= dv[j] ? static_cast<int>(2 * sizeof(T)) : static_cast<int>(sizeof(T)));
+    }
+    uint64_t cur[GS];
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+      // a = sizeof(T) (63 + k), k in [0, 63]; S_63 sits at E[63], read at
+      // offset (a - 63 sizeof(T)) | 63 sizeof(T) = (k | 63) sizeof(T), which
+      // is 63 sizeof(T) for every k in [0, 63] (sizeof(T) a power of two), so
+      // that the read stays with the search: a constant LDS address would be
+      // hoisted out of the cell loop into a register per slot
+      const T last = *reinterpret_cast<const T*>(eb + j * kSortWidth * sizeof(T) +
+                                                 ((a[j] - 63 * static_cast<int>(sizeof(T))) |
+                                                  (63 * static_cast<int>(sizeof(T)))));
+      int k = a[j] / static_cast<int>(sizeof(T)) - (kSortWidth - 1);
+      k += static_cast<int>(k == kSortWidth - 1) & static_cast<int>(last <= dv[j]);
+      cur[j] = P[(g * GS + j) * kMaskPitch + k];
+    }
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+      acc |= pend[j];
+      pend[j] = cur[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < GS; ++j) acc |= pend[j];
+  lo = static_cast<uint32_t>(acc);
+  hi = static_cast<uint32_t>(acc >> 32);
+}
+
 // Threads and LDS batches of the ionisation pass: one cell per thread over a
 // row pair (2N cells), FFT teams of TS threads, WB walkers per LDS batch.
 template <int N>
@@ -668,11 +848,21 @@ struct IonShape {
 // smoothed boxes are read once per group.  Two real rows are transformed as
 // one complex row.  Output: spec[w][row][kx < N/2] (streaming stores), the
 // Nyquist plane nyq[w][y][z], and per-block x_HI sums xpart[w][block].
-template <typename T, typename S, int N, bool TWO>
+// The x_HI sums are FP64 above the first level: each 16-lane row of a wave
+// adds its 16 values in a 4-level pairwise FP32 tree (relative error at most
+// 4 units of FP32 rounding for these non-negative terms), everything after
+// that in double.
+// FIELDS: walker fw of the group also writes its x_HI and dT_b boxes (fx, fd,
+// N^3 values each) from the same per-cell values that enter its spectrum.
+// SORTED: the flag test of the whole group from the sorted tables (Eg, Pg)
+// built by k_slot_tables for the same thresholds (constant efficiency only).
+template <typename T, typename S, int N, bool TWO, bool FIELDS, bool SORTED>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ odens, int nr, const WalkerConst<T>* __restrict__ wc,
     const T* __restrict__ thr, const T* __restrict__ zt, int nw, T tb, T dc, cplx<T>* __restrict__ spec,
-    cplx<T>* __restrict__ nyq, double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride) {
+    cplx<T>* __restrict__ nyq, double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride, int fw,
+    T* __restrict__ fx, T* __restrict__ fd, const T* __restrict__ Eg, const uint64_t* __restrict__ Pg) {
+  static_assert(!(SORTED && TWO), "the sorted flag test covers one-sided thresholds only");
   using IS = IonShape<N>;
   constexpr size_t N3 = static_cast<size_t>(N) * N * N;
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
@@ -686,27 +876,59 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   const int lane = t & 63;
   const int row = t / N, x = t % N;
   T* ldsr = reinterpret_cast<T*>(lds);
+  // SORTED: the search trees of the group's slots, E[nr][64] (dynamic LDS)
+  HIP_DYNAMIC_SHARED(unsigned char, ion_dyn)
+  T* El = reinterpret_cast<T*>(ion_dyn);
+  if constexpr (SORTED)
+    for (int e = t; e < kNrMax * kSortWidth; e += IS::NT) El[e] = Eg[e];
   for (int w = t; w < kMaxGroup; w += IS::NT) acc[w] = 0.0;
   load_twiddles<N>(twl, tw, tstride);
   for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
     const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
-    T d[kNrMax];
-    load_radii<T, S>(dR, N3, cell, nr, d);
+    // ballot test: every slot's delta_R in registers for the walker loop;
+    // sorted test: the cell's walker mask first, then only the cell radius
+    T d[SORTED ? 1 : kNrMax];
+    uint32_t mlo = 0, mhi = 0;
+    if constexpr (SORTED) {
+      sorted_flags<T, S>(dR, N3, cell, nr, El, Pg, mlo, mhi);
+      d[0] = load_as<T>(dR, static_cast<size_t>(nr - 1) * N3 + cell);
+    } else {
+      load_radii<T, S>(dR, N3, cell, nr, d);
+    }
     const T od = odens[cell];
     // Every delta_R of the cell is in its register before the walker loop:
     // otherwise the compiler, unable to see that the loads have landed after
     // the first walker, keeps one load-counter wait per radius inside the loop
     // for every walker (an empty asm taking the values, no instruction).
 #pragma unroll
-    for (int s = 0; s < kNrMax; ++s) asm volatile("" ::"v"(d[s]));
+    for (int s = 0; s < (SORTED ? 1 : kNrMax); ++s) asm volatile("" ::"v"(d[s]));
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        const T xh = cell_xhi<T, kNrMax, TWO>(d, load_walker(wc + w), thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
-                                              zt + static_cast<size_t>(w) * kZetaPitch, dc);
-        ldsr[2 * (q * N + x) + row] = tb * xh * od;
+        T xh;
+        if constexpr (SORTED) {
+          const WalkerConst<T> c = load_walker(wc + w);
+          const uint32_t half = w < 32 ? mlo : mhi;
+          xh = T(1);
+          if ((half >> (w & 31)) & 1u)
+            xh = T(0);
+          else if (c.partial)
+            xh = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
+        } else {
+          xh = cell_xhi<T, (SORTED ? 1 : kNrMax), TWO>(d, load_walker(wc + w),
+                                                       thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
+                                                       zt + static_cast<size_t>(w) * kZetaPitch, dc);
+        }
+        const T tv = tb * xh * od;
+        ldsr[2 * (q * N + x) + row] = tv;
+        if constexpr (FIELDS) {
+          if (w == fw) {
+            fx[cell] = xh;
+            fd[cell] = tv;
+          }
+        }
         if constexpr (IS::NT >= 64) {
           const T s = row_sum(xh);
           if ((lane & 15) == 0) wsum[q][t >> 4] = s;
@@ -759,24 +981,6 @@ __global__ __launch_bounds__(256) void k_los_factor(const T* __restrict__ delta,
   }
 }
 
-// Materialise x_HI and dT_b of one walker (same per-cell arithmetic as above).
-template <typename T, typename S, int N, bool TWO>
-__global__ __launch_bounds__(256) void k_materialize(const S* __restrict__ dR, const T* __restrict__ odens, int nr,
-                                                     const WalkerConst<T>* __restrict__ wc,
-                                                     const T* __restrict__ thr, const T* __restrict__ zt, T tb,
-                                                     T dc, T* __restrict__ xhi, T* __restrict__ dtb) {
-  constexpr size_t N3 = static_cast<size_t>(N) * N * N;
-  const WalkerConst<T> c = wc[0];
-  for (size_t cell = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; cell < N3;
-       cell += static_cast<size_t>(gridDim.x) * 256) {
-    T d[kNrMax];
-    load_radii<T, S>(dR, N3, cell, nr, d);
-    const T x = cell_xhi<T, kNrMax, TWO>(d, c, thr, zt, dc);
-    if (xhi) xhi[cell] = x;
-    if (dtb) dtb[cell] = tb * x * odens[cell];
-  }
-}
-
 // Deterministic final reduction for one walker per block:
 // pk[b] = pscale * sum_tiles part / counts[b]; xhi = inv_cells * sum xpart.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, long ntiles, int nbins,
@@ -811,6 +1015,12 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     __syncthreads();
   }
   if (pk && t >= nbins && t < nbins_out) pk[w * pk_stride + t] = 0.0;
+}
+
+// y[i] = erfc(x[i]) by the FP32 routine of the ionisation pass.
+__global__ __launch_bounds__(256) void k_erfc(const float* __restrict__ x, float* __restrict__ y, size_t n) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += static_cast<size_t>(gridDim.x) * 256)
+    y[i] = erfc_fast(x[i]);
 }
 
 template <typename T, typename S>
@@ -882,28 +1092,75 @@ long axis_tiles(int n, long inner) {
   return ti > 0 ? (inner + ti - 1) / ti : 0;
 }
 
+// Tiles of the binning pass with at least one column (ky, kx) inside the
+// disk ny^2 + kx^2 <= (n/2)^2, in increasing order.
+std::vector<int32_t> bins_live_tiles(int n) {
+  std::vector<int32_t> out;
+  (void)with_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    using BT = BinTiles<N, AxisShape<N>::TI>;
+    for (long t = 0; t < BT::COUNT; ++t) {
+      bool live = false;
+      for (int cc = 0; cc < AxisShape<N>::TI && !live; ++cc) {
+        int ky, kx;
+        BT::column(t, cc, ky, kx);
+        const int ny = ky < N / 2 ? ky : ky - N;
+        live = ky >= 0 && ny * ny + kx * kx <= (N / 2) * (N / 2);
+      }
+      if (live) out.push_back(static_cast<int32_t>(t));
+    }
+    return hipSuccess;
+  });
+  return out;
+}
+
+long bins_live_count(int n) {
+  static long cache[10] = {};
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  if (l < 10 && cache[l] == 0) cache[l] = static_cast<long>(bins_live_tiles(n).size());
+  return l < 10 ? cache[l] : 0;
+}
+
 // Blocks per spectrum of the binning pass: enough blocks over `outer`
-// spectra to fill the chip, each walking every parts-th tile.
+// spectra to fill the chip, each walking every parts-th live tile.
 long bins_parts(int n, long outer) {
-  const long count = bins_tiles(n);
+  const long count = bins_live_count(n);
   const long k = (kPipeBlocks + outer - 1) / outer;
   return k < 1 ? 1 : (k > count ? count : k);
 }
 
-// Bins per launch of the binning pass: its slot array (bins x threads) and
-// its static LDS stay within 128 KB per block where they can; at least one
-// bin (FP64 at N = 512 then uses 144 KB of the CU's 160 KB).  (The CPU
-// emulation used by the tests lowers the budget so that FP64 at N = 16 takes
+// LDS budget of one binning block (static tile + twiddles + FP64 slots).
+// (The CPU emulation used by the tests lowers it so that FP64 at N = 16 takes
 // several launches.)
 #ifndef XS21_BINS_LDS_BUDGET
 #define XS21_BINS_LDS_BUDGET 131072
 #endif
-template <typename T, int N>
-constexpr int bins_per_launch() {
-  using A = AxisShape<N>;
-  constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
-  constexpr long per = (XS21_BINS_LDS_BUDGET - stat) / (static_cast<long>(A::NT) * static_cast<long>(sizeof(T)));
-  return per < 1 ? 1 : static_cast<int>(per);
+
+// Slot rows for bins [b0, b1) at size N with M = N / TS outputs per team
+// member: member j outputs kz in [j M, j M + M), so none of its modes lies
+// below the bin of min |nz|^2 over that range (|n|^2 >= nz^2; the DC mode is
+// never binned, so at least 1).
+template <int N, int TS>
+BinSlots bin_slots(const int8_t* bintab_host, int b0, int b1) {
+  constexpr int M = N / TS;
+  BinSlots bs{};
+  int rows = 0;
+  for (int j = 0; j < TS; ++j) {
+    int nzmin = N;
+    for (int kz = j * M; kz < j * M + M; ++kz) {
+      const int nz = kz < N / 2 ? kz : N - kz;
+      nzmin = nz < nzmin ? nz : nzmin;
+    }
+    const int n2 = nzmin * nzmin > 0 ? nzmin * nzmin : 1;
+    int lo = bintab_host[n2];
+    lo = lo > b0 ? lo : b0;
+    bs.lo[j] = static_cast<int16_t>(lo);
+    bs.base[j] = static_cast<int16_t>(rows);
+    rows += b1 > lo ? b1 - lo : 0;
+  }
+  bs.rows = rows;
+  return bs;
 }
 
 long bins_tiles(int n) {
@@ -1027,6 +1284,28 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
   });
 }
 
+hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long inner, long ilim, bool nyquist,
+                                const void* tw, int ntab, hipStream_t s) {
+  return with_real(dtype, [&](auto tv) {
+    using T = decltype(tv);
+    return with_n(n, [&](auto nc) {
+      constexpr int N = decltype(nc)::value;
+      using A = AxisShape<N>;
+      if (ilim < 1 || ilim > inner || ilim % A::TI != 0 || outer < 1)   // not whole tiles: the plain pass
+        return launch_axis(dtype, n, -1, 0, data, data, outer, inner, ilim, nullptr, 1, 0, 0, tw, ntab, s);
+      const long ntiles = ilim / A::TI * outer;
+      auto* dp = static_cast<cplx<T>*>(data);
+      if (nyquist)
+        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 2>), dim3(grid_for(ntiles, kPipeBlocks)), dim3(A::NT), 0, s, dp, dp,
+                           inner, ilim / A::TI, ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
+      else
+        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 1>), dim3(grid_for(ntiles, kPipeBlocks)), dim3(A::NT), 0, s, dp, dp,
+                           inner, ilim / A::TI, ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
+      return hipGetLastError();
+    });
+  });
+}
+
 int axis_tile_cols(int n) {
   int ti = 0;
   (void)with_n(n, [&](auto nc) {
@@ -1072,74 +1351,98 @@ hipError_t launch_axis_live_y(int dtype, int n, void* data, long inner, long ili
 }
 
 hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, long parts,
-                            const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
-  if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535 || parts < 1 || parts > bins_tiles(n))
+                            const int32_t* tiles, long ntiles, const int8_t* bintab, const int8_t* bintab_host,
+                            int nbins, double* part, const void* tw, int ntab, hipStream_t s) {
+  if (nbins < 1 || nbins > kMaxBins || outer < 1 || outer > 65535 || ntiles < 1 || ntiles > bins_tiles(n) ||
+      parts < 1 || parts > ntiles || !bintab_host || !tiles)
     return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
       constexpr int N = decltype(nc)::value;
       using A = AxisShape<N>;
-      constexpr int per = bins_per_launch<T, N>();
+      constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
+      const auto slot_bytes = [](const BinSlots& bs) { return static_cast<long>(bs.rows) * A::TI * 8; };
       hipError_t e = hipSuccess;
-      for (int b0 = 0; b0 < nbins && e == hipSuccess; b0 += per) {
-        const int nbc = nbins - b0 < per ? nbins - b0 : per;
+      for (int b0 = 0; b0 < nbins && e == hipSuccess;) {
+        // the widest bin range [b0, b1) whose slots fit the budget (at least one bin)
+        int b1 = b0 + 1;
+        BinSlots bs = bin_slots<N, A::TS>(bintab_host, b0, b1);
+        while (b1 < nbins) {
+          const BinSlots wider = bin_slots<N, A::TS>(bintab_host, b0, b1 + 1);
+          if (stat + slot_bytes(wider) > XS21_BINS_LDS_BUDGET) break;
+          bs = wider;
+          ++b1;
+        }
         hipLaunchKernelGGL((k_axis_bins<T, N>), dim3(static_cast<unsigned>(outer * parts)), dim3(A::NT),
-                           static_cast<size_t>(nbc) * A::NT * sizeof(T), s, static_cast<const cplx<T>*>(src),
-                           static_cast<const cplx<T>*>(nyq), parts,
-                           bintab, nbins, b0, nbc, part, static_cast<const cplx<T>*>(tw), ntab / N);
+                           static_cast<size_t>(slot_bytes(bs)), s, static_cast<const cplx<T>*>(src),
+                           static_cast<const cplx<T>*>(nyq), parts, tiles, ntiles, bintab, nbins, b0, b1 - b0, bs,
+                           part, static_cast<const cplx<T>*>(tw), ntab / N);
         e = hipGetLastError();
+        b0 = b1;
       }
       return e;
     });
   });
 }
 
-hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
-                      const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
-                      double* xpart, const void* tw, int ntab, hipStream_t s) {
-  if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
-  return with_real(dtype, [&](auto tv) {
-    using T = decltype(tv);
-    return with_storage<T>(storage, [&](auto sv) {
-      using ST = decltype(sv);
-      return with_n(n, [&](auto nc) {
-        constexpr int N = decltype(nc)::value;
-        auto go = [&](auto two) {
-          hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value>), dim3(ion_grid(N)), dim3(IonShape<N>::NT),
-                             0, s, static_cast<const ST*>(dR), static_cast<const T*>(odens), nr,
-                             static_cast<const WalkerConst<T>*>(wc), static_cast<const T*>(thr),
-                             static_cast<const T*>(zt), nw, static_cast<T>(tb), static_cast<T>(dc),
-                             static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,
-                             static_cast<const cplx<T>*>(tw), ntab / N);
-          return hipGetLastError();
-        };
-        return zt ? go(std::true_type{}) : go(std::false_type{});
-      });
-    });
-  });
+// Flag test of the constant-efficiency FP32 ionisation pass: the sorted
+// tables (default) or one compare per walker and radius (XS21_ION_FLAGS =
+// "ballot"), read once.
+bool ion_sorted_default() {
+  static const bool v = [] {
+    const char* e = std::getenv("XS21_ION_FLAGS");
+    return !(e && std::strcmp(e, "ballot") == 0);
+  }();
+  return v;
 }
 
-hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
-                              const void* wc, const void* thr, const void* zt, double tb, double dc, void* xhi,
-                              void* dtb, hipStream_t s) {
-  if (nr < 1 || nr > kNrMax) return hipErrorInvalidValue;
+size_t slot_table_bytes() {
+  return static_cast<size_t>(kNrMax) * kSortWidth * sizeof(double) +
+         static_cast<size_t>(kNrMax) * kMaskPitch * sizeof(uint64_t);
+}
+
+hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
+                      const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
+                      double* xpart, const void* tw, int ntab, hipStream_t s, int field_walker, void* x_hi,
+                      void* dtb, void* slot_tab) {
+  if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
+  const bool fields = field_walker >= 0;
+  if (fields && (field_walker >= nw || !x_hi || !dtb)) return hipErrorInvalidValue;
+  const bool sorted = slot_tab && !zt && dtype == kF32 && ion_sorted_default();
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_storage<T>(storage, [&](auto sv) {
       using ST = decltype(sv);
       return with_n(n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
-        const long cells = static_cast<long>(N) * N * N;
-        auto go = [&](auto two) {
-          hipLaunchKernelGGL((k_materialize<T, ST, N, decltype(two)::value>),
-                             dim3(grid_for((cells + 255) / 256, 16384)), dim3(256), 0, s, static_cast<const ST*>(dR),
+        T* E = static_cast<T*>(slot_tab);
+        uint64_t* P = reinterpret_cast<uint64_t*>(static_cast<unsigned char*>(slot_tab) +
+                                                  static_cast<size_t>(kNrMax) * kSortWidth * sizeof(double));
+        auto go = [&](auto two, auto withf, auto srt) {
+          constexpr bool SRT = decltype(srt)::value && !decltype(two)::value && std::is_same<T, float>::value;
+          const size_t dyn = SRT ? static_cast<size_t>(kNrMax) * kSortWidth * sizeof(T) : 0;
+          hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value, decltype(withf)::value, SRT>),
+                             dim3(ion_grid(N)), dim3(IonShape<N>::NT), dyn, s, static_cast<const ST*>(dR),
                              static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc),
-                             static_cast<const T*>(thr), static_cast<const T*>(zt), static_cast<T>(tb),
-                             static_cast<T>(dc), static_cast<T*>(xhi), static_cast<T*>(dtb));
+                             static_cast<const T*>(thr), static_cast<const T*>(zt), nw, static_cast<T>(tb),
+                             static_cast<T>(dc), static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,
+                             static_cast<const cplx<T>*>(tw), ntab / N, field_walker, static_cast<T*>(x_hi),
+                             static_cast<T*>(dtb), static_cast<const T*>(E), static_cast<const uint64_t*>(P));
           return hipGetLastError();
         };
-        return zt ? go(std::true_type{}) : go(std::false_type{});
+        if (zt) return fields ? go(std::true_type{}, std::true_type{}, std::false_type{})
+                              : go(std::true_type{}, std::false_type{}, std::false_type{});
+        if (sorted) {
+          hipLaunchKernelGGL((k_slot_tables<T>), dim3(static_cast<unsigned>(kNrMax)), dim3(kSortWidth), 0, s,
+                             static_cast<const T*>(thr), nw, E, P);
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return e;
+          return fields ? go(std::false_type{}, std::true_type{}, std::true_type{})
+                        : go(std::false_type{}, std::false_type{}, std::true_type{});
+        }
+        return fields ? go(std::false_type{}, std::true_type{}, std::false_type{})
+                      : go(std::false_type{}, std::false_type{}, std::false_type{});
       });
     });
   });
@@ -1163,6 +1466,12 @@ hipError_t launch_los_factor(int dtype, const void* delta, const void* g, void* 
                        static_cast<T>(tmax));
     return hipGetLastError();
   });
+}
+
+hipError_t launch_erfc(const float* x, float* y, size_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_erfc, dim3(grid_for(static_cast<long>((count + 255) / 256), 4096)), dim3(256), 0, s, x, y,
+                     count);
+  return hipGetLastError();
 }
 
 hipError_t launch_cast(int dtype, int storage, const void* in, void* out, size_t count, hipStream_t s) {

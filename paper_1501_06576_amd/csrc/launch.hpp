@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace xs21 {
 
 // Element types; values match xs21_dtype.
@@ -15,7 +17,7 @@ constexpr int kBF16 = 2;
 int axis_tile(int n);                   // inner columns per block of the strided passes
 long axis_tiles(int n, long inner);     // blocks along the inner dimension
 long bins_tiles(int n);                 // column tiles per spectrum of the binning z pass
-long bins_parts(int n, long outer);     // partial sums per spectrum written by the binning pass
+long bins_parts(int n, long outer);     // partial sums per spectrum written by the binning pass (<= live tiles)
 int ion_grid(int n);                    // blocks of the ionisation pass
 int max_group();                        // walkers per ionisation launch
 int max_radii();                        // radii per ladder
@@ -67,21 +69,37 @@ hipError_t launch_axis_live_y(int dtype, int n, void* data, long inner, long ili
 // Forward z pass of `outer` padded spectra [n][n][half_pitch(n)] (kx < n/2)
 // and their Nyquist planes nyq[outer][ky][z], fused with |X|^2 binning into
 // part[outer][parts][nbins] (FP64); parts in [1, bins_tiles(n)], normally
-// bins_parts(n, outer).
+// bins_parts(n, outer).  bintab / bintab_host: the bin of every |n|^2 on the
+// device and on the host (the host copy sizes each launch's FP64 slots).
+// The tiles are entries [0, ntiles) of the device list `tiles` (normally
+// bins_live_tiles(n): no other tile holds a binned mode).
 hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, long outer, long parts,
-                            const int8_t* bintab, int nbins, double* part, const void* tw, int ntab, hipStream_t s);
+                            const int32_t* tiles, long ntiles, const int8_t* bintab, const int8_t* bintab_host,
+                            int nbins, double* part, const void* tw, int ntab, hipStream_t s);
+// Tiles of the binning pass holding a column with ny^2 + kx^2 <= (n/2)^2.
+std::vector<int32_t> bins_live_tiles(int n);
+long bins_live_count(int n);
+// Forward y pass, in place, of `outer` slices [n][inner] over columns
+// [0, ilim) of spectra that are only binned afterwards: outputs with
+// ny^2 + kx^2 > (n/2)^2 are not stored (kx = the column index, or n/2 for
+// every column when nyquist, the Nyquist plane [ky][z]).
+hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long inner, long ilim, bool nyquist,
+                                const void* tw, int ntab, hipStream_t s);
 // Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
 // [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
 // zt == nullptr: constant efficiency, thr[w][max_radii()]; else the
 // two-population efficiency, thr[w][2][max_radii()] (lo, hi) and the cell
 // radius tables zt[w][kZetaPitch] written by launch_plan2.
+// field_walker >= 0: walker field_walker of the group also writes its x_HI
+// and dT_b boxes (n^3 values of dtype each) to x_hi and dtb, from the same
+// launch (field_walker < 0: no fields, x_hi / dtb ignored).
+// slot_tab: device scratch of slot_table_bytes() for the sorted flag test of
+// FP32 constant-efficiency walkers (nullptr: one compare per walker and radius).
+size_t slot_table_bytes();
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
                       const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
-                      double* xpart, const void* tw, int ntab, hipStream_t s);
-// x_HI and dT_b boxes of one walker (either output may be null); zt as above.
-hipError_t launch_materialize(int dtype, int storage, int n, const void* dR, const void* odens, int nr,
-                              const void* wc, const void* thr, const void* zt, double tb, double dc, void* xhi,
-                              void* dtb, hipStream_t s);
+                      double* xpart, const void* tw, int ntab, hipStream_t s, int field_walker = -1,
+                      void* x_hi = nullptr, void* dtb = nullptr, void* slot_tab = nullptr);
 // Two-population planning (Section 4, eq. 9) of nw walkers on one box:
 // slots[nr] (device, slot 0 = cell radius), wp[nw] (device) -> thresholds
 // thr[w][2][stride] (lo, hi; +inf where unused), wc[w].upper set where some
@@ -121,6 +139,15 @@ hipError_t launch_chi2(const double* pk, long pk_stride, int nw, const double* t
 // 1 + delta), the density factor of dT_b with the velocity-gradient term.
 hipError_t launch_los_factor(int dtype, const void* delta, const void* g, void* odens, size_t count, double tmax,
                              hipStream_t s);
+// Bandwidth probe `kind` (0 read, 1 write, 2 copy first half -> second half,
+// 3 strided 128-byte tiles of 256^3 half spectra) over buf[0, bytes); sink:
+// probe_sink_bytes() of device memory for the read kernels' block sums;
+// *moved: HBM bytes one launch reads plus writes.
+size_t probe_sink_bytes();
+size_t probe_tile_spectrum_bytes();
+hipError_t launch_probe(int kind, void* buf, size_t bytes, float* sink, double* moved, hipStream_t s);
+// y[i] = erfc(x[i]) for `count` values by the FP32 erfc of the ionisation pass.
+hipError_t launch_erfc(const float* x, float* y, size_t count, hipStream_t s);
 // out[i] = (dtype) in[i] for `count` stored values.
 hipError_t launch_cast(int dtype, int storage, const void* in, void* out, size_t count, hipStream_t s);
 

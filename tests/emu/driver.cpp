@@ -20,6 +20,8 @@
 //   materialize2 <box> <walker2> -> mat2_b{b}_w{w}_{xhi,dtb}.bin
 //   mcmc <dim> <a> <nw> <steps> <lo/hi file> <x file> <u file> <tag>
 //        -> mcmc<tag>_x.bin [steps+1][nw][dim], _lp.bin [steps+1][nw], _acc.bin [steps][nw] int32
+//   batch_fields <nbmax> <walker> <box> -> batchf_{pk,xhi,fx,fd}.bin (fields of that walker on that box)
+//   erfc <file> <count>        -> erfc.bin: the FP32 erfc of the ionisation pass at count floats
 //   smoothed <box> <index>     -> sm_b{b}_j{j}.bin
 //   pk <box> <field file>      -> fpk_b{b}.bin
 #include <cstdio>
@@ -118,6 +120,34 @@ int main(int argc, char** argv) {
       CHECK(xs21_sync(ctx));
       write_file(out + "/batch2" + tag + "_pk.bin", pk.data(), pk.size() * 8);
       write_file(out + "/batch2" + tag + "_xhi.bin", xm.data(), xm.size() * 8);
+    } else if (cmd == "batch_fields") {
+      const int nb = static_cast<int>(box_n.size());
+      std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
+      int nbmax = 0, fw = 0, fb = 0;
+      is >> nbmax >> fw >> fb;
+      const int nw = static_cast<int>(walkers.size());
+      const size_t cells = static_cast<size_t>(box_n[fb]) * box_n[fb] * box_n[fb];
+      const size_t rs = box_dtype[fb] == XS21_F64 ? 8 : 4;
+      std::vector<double> pk(static_cast<size_t>(nw) * nb * nbmax, -1.0), xm(static_cast<size_t>(nw) * nb, -1.0);
+      std::vector<char> fx(cells * rs), fd(cells * rs);
+      CHECK(xs21_eval_batch_fields(ctx, bx.data(), nb, walkers.data(), nw, pk.data(), xm.data(), fw, fb, fx.data(),
+                                   fd.data()));
+      CHECK(xs21_sync(ctx));
+      write_file(out + "/batchf_pk.bin", pk.data(), pk.size() * 8);
+      write_file(out + "/batchf_xhi.bin", xm.data(), xm.size() * 8);
+      write_file(out + "/batchf_fx.bin", fx.data(), fx.size());
+      write_file(out + "/batchf_fd.bin", fd.data(), fd.size());
+    } else if (cmd == "erfc") {
+      std::string f;
+      long count = 0;
+      is >> f >> count;
+      auto xv = read_file(f);
+      std::vector<float> y(count);
+      if (!ctx) CHECK(xs21_create(&ctx, 0, nullptr, &phys));
+      CHECK(xs21_erfc_f32(ctx, reinterpret_cast<const float*>(xv.data()), y.data(), count));
+      CHECK(xs21_sync(ctx));
+      write_file(out + "/erfc.bin", y.data(), y.size() * 4);
     } else if (cmd == "materialize2") {
       int b, w;
       is >> b >> w;

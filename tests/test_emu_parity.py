@@ -340,3 +340,62 @@ def test_emu_mcmc_chain(dim):
     np.testing.assert_allclose(gx, ox, rtol=1e-12)
     tol = 1e-9 if dim == 3 else 1e-5
     np.testing.assert_allclose(glp, olp, rtol=tol, atol=0 if dim == 3 else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_emu_batch_fields_mid_group(dtype):
+    """Fields written by the batched ionisation launch for a walker in the middle
+    of a later walker group, on the second of two boxes, against the oracle cell by
+    cell; the same call's P(k) equals the plain batch's bit for bit."""
+    npd = np.float64 if dtype == "f64" else np.float32
+    specs = [(16, 24.0, 8.0, 4), (16, 32.0, 9.0, 5)]
+    walkers = [(30.0, 15.0, 5e4), (12.0, 8.0, 2e5), (80.0, 19.0, 1.2e4), (45.0, 6.0, 3e4), (9.0, 14.0, 7e4),
+               (0.7, 10.0, 2e4)]
+    run = eh.EmuRun(storage=dtype, max_walkers=4, phys={"pk_amp": AMP})
+    boxes = []
+    for i, (n, box, z, nb) in enumerate(specs):
+        d = synth.make_box(n, box, z, seed=70 + i, amp=AMP, dtype=npd)
+        boxes.append(d)
+        run.box(d, box, z, nb)
+    for w in walkers:
+        run.walker(*w)
+    run.cmd("prepare")
+    run.cmd("batch 5")
+    run.cmd("batch_fields 5 4 1")     # walker 4 = second slot of the second group of 4
+    run.run()
+    pk = run.read("batch_pk.bin", np.float64)
+    np.testing.assert_array_equal(run.read("batchf_pk.bin", np.float64), pk)
+    np.testing.assert_array_equal(run.read("batchf_xhi.bin", np.float64), run.read("batch_xhi.bin", np.float64))
+    n, box, z, nb = specs[1]
+    w = walkers[4]
+    ev = oracle.evaluate(boxes[1], box, z, w, oracle.walker_radii(oracle.shared_radii(n, box, PHYS), w[1]), nb, PHYS)
+    x = run.read("batchf_fx.bin", npd, (n, n, n)).astype(np.float64)
+    d = run.read("batchf_fd.bin", npd, (n, n, n)).astype(np.float64)
+    assert np.array_equal(x == 0, ev.flagged)
+    same = (x == 0) == ev.flagged
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert np.abs(x - ev.x_hi)[same].max() <= tol
+    assert np.abs(d - ev.dtb)[same].max() <= tol * np.abs(ev.dtb).max()
+
+
+def test_emu_erfc_f32():
+    """The FP32 erfc of the ionisation pass (Numerical Recipes' Chebyshev fit,
+    fractional error < 1.2e-7) against math.erfc at the same float inputs, over
+    [-3, 8] and densely over [0, 4], where the partial ionisation evaluates it.
+    Besides the fit's own error, single precision rounds the exponent
+    -z^2 + P(t) once (relative error of the result up to about (z^2 + 2) ulp),
+    and t, P and the product a few times; the bound allows 1.2e-7 plus
+    (2 z^2 + 8) units of 2^-24."""
+    import math
+    xs = np.concatenate([np.linspace(-3.0, 8.0, 4001), np.linspace(0.0, 4.0, 4001)]).astype(np.float32)
+    run = eh.EmuRun(storage="f32", max_walkers=1, phys={"pk_amp": AMP})
+    path = run.write_array("erfc_x.bin", xs)
+    run.cmd(f"erfc {path} {xs.size}")
+    run.run()
+    y = run.read("erfc.bin", np.float32).astype(np.float64)
+    ref = np.array([math.erfc(float(v)) for v in xs])
+    z = np.abs(xs.astype(np.float64))
+    rel = np.abs(y / ref - 1.0)
+    bound = 1.2e-7 + (2.0 * z * z + 8.0) * 2.0 ** -24
+    worst = int(np.argmax(rel / bound))
+    assert np.all(rel <= bound), f"x = {xs[worst]}: relative error {rel[worst]:.3e} > {bound[worst]:.3e}"
