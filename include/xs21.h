@@ -266,6 +266,21 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
  * context, prepared or not.  Asynchronous. */
 xs21_status xs21_erfc_f32(xs21_ctx* ctx, const float* x, float* y, long n);
 
+/* xs21_power_spectrum for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels, with the spectrum, its Nyquist plane and the
+ * partial bin sums in one statically allocated device array of 20 MiB per
+ * device (the library holds it until the process ends) instead of the
+ * workspace's evaluation scratch.  It allocates nothing and does not
+ * synchronise.  field: DEVICE, n^3 values of the box dtype; pk_dev: DEVICE,
+ * n_bins doubles (P_b as xs21_power_spectrum returns them).  Asynchronous on
+ * the context stream.  EINVAL when the box needs more scratch than 20 MiB
+ * (FP32 boxes up to 128^3 fit, FP64 boxes up to 64^3); the message gives both
+ * sizes.  Every call on one device shares the array: calls that overlap on
+ * one device (several streams or contexts) race and must be ordered by the
+ * caller; nothing in the array needs clearing between calls. */
+xs21_status xs21_power_spectrum_static(xs21_ctx* ctx, xs21_box box, const void* field, double* pk_dev);
+
 /* Likelihood epilogue (Section 2.5; redshifts combined as in Section 3.4).
  * Sets the mock observation of `box`: delta2_mock[b] is the mock
  * Delta^2_21 (mK^2) on the box's own bins and noise_sigma[b] its

@@ -95,6 +95,7 @@ _SIGNATURES = {
     "xs21_power_spectrum": (_I, [_P, _I, _P, _DP]),
     "xs21_resmooth": (_I, [_P, _I, _P]),
     "xs21_erfc_f32": (_I, [_P, _P, _P, ctypes.c_long]),
+    "xs21_power_spectrum_static": (_I, [_P, _I, _P, _P]),
     "xs21_probe_bandwidth": (_I, [_P, _I, _P, ctypes.c_size_t, _I, _DP, _DP]),
     "xs21_set_mock": (_I, [_P, _I, _DP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "xs21_chi2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P]),
@@ -418,6 +419,18 @@ class Context:
         _check(library().xs21_erfc_f32(self._ctx, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                        t.numel()))
         return y
+
+    def power_spectrum_static(self, box: int, field, pk=None):
+        """P(k) of a device field through the allocation-free entry point (static device
+        scratch); returns a device float64 tensor of n_bins (asynchronous)."""
+        b = self.boxes[box]
+        f = field.contiguous()
+        if pk is None:
+            pk = self.torch.empty(b["n_bins"], dtype=self.torch.float64, device=self.device)
+        self._dev(pk, (b["n_bins"],), self.torch.float64, "pk")
+        _check(library().xs21_power_spectrum_static(self._ctx, box, ctypes.c_void_p(f.data_ptr()),
+                                                    ctypes.c_void_p(pk.data_ptr())))
+        return pk
 
     def set_mock(self, box: int, delta2_mock, noise_sigma=None, model_err=0.25, k_lo=0.15, k_hi=1.0):
         """Mock Delta^2 (and optional noise) of `box` for the chi^2 epilogue; host arrays of n_bins."""

@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxs21.so")
-SOURCES = ["kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "api.cpp",
-           "plan.cpp"]
+SOURCES = ["kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "static_scratch.hip",
+           "api.cpp", "plan.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",

@@ -16,6 +16,7 @@
 
 #include "../../include/xs21.h"
 #include "common.hpp"
+#include "internal.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -673,6 +674,13 @@ xs21_status xs21_create(xs21_ctx** out, int hip_device, void* hip_stream, const 
     delete c;
     return fail(XS21_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
   }
+  // the static scratch array's address on this device (once per device)
+  e = xs21::static_scratch_init(hip_device);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(c->upload_done);
+    delete c;
+    return fail(XS21_EDEVICE, "static scratch lookup (hipGetSymbolAddress): %s", hipGetErrorString(e));
+  }
   *out = c;
   return XS21_OK;
 }
@@ -1309,6 +1317,49 @@ xs21_status xs21_smoothed(xs21_ctx* ctx, xs21_box box, int index, void* out) {
   return XS21_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch bytes of one P(k) of box b: a padded half spectrum, its Nyquist
+// plane and the binning pass's FP64 partial sums.
+size_t pk_scratch_bytes(const BoxRec& b) {
+  return align_up(b.spec_bytes()) + align_up(nyq_bytes(b)) +
+         align_up(static_cast<size_t>(xs21::bins_parts(b.n, 1)) * b.nbins * 8);
+}
+
+// Binned P(k) of a device field on box b's geometry into pk_dev (device,
+// n_bins doubles), with `scratch` (device, pk_scratch_bytes(b)) for the
+// spectrum, Nyquist plane and partial sums; asynchronous on the ctx stream.
+hipError_t power_spectrum_into(xs21_ctx* ctx, const BoxRec& b, const void* field, unsigned char* scratch,
+                               double* pk_dev) {
+  const long n = b.n, hp = static_cast<long>(b.pitch());
+  // same layout and passes as one walker's spectrum in an evaluation
+  const EvalSlot sl = eval_slot(b, scratch, 1);
+  const long parts = xs21::bins_parts(b.n, 1);
+  const void* tw = tw_ptr(ctx, b.dtype);
+  hipError_t e = xs21::launch_rows_r2c(b.dtype, b.n, field, sl.spec, sl.nyq, n * n, tw, kNtab, ctx->stream);
+  if (e == hipSuccess) e = xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, n, hp, n / 2, false, tw, kNtab, ctx->stream);
+  if (e == hipSuccess) e = xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, 1, n, n, true, tw, kNtab, ctx->stream);
+  if (e == hipSuccess)
+    e = xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1, parts,
+                               reinterpret_cast<const int32_t*>(ctx->ws + b.off_bins_live),
+                               static_cast<long>(b.bins_live.size()),
+                               reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.bintab.data(), b.nbins,
+                               sl.part, tw, kNtab, ctx->stream);
+  const double L3 = b.box * b.box * b.box;
+  if (e == hipSuccess)
+    e = xs21::launch_finalize(1, sl.part, parts, b.nbins, nullptr, 0,
+                              reinterpret_cast<const double*>(ctx->ws + b.off_counts),
+                              L3 / std::pow(static_cast<double>(n), 6), 1.0, pk_dev, b.nbins, b.nbins, nullptr, 0,
+                              ctx->stream);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
@@ -1316,28 +1367,27 @@ xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, 
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!field || !pk) return fail(XS21_EINVAL, "null argument");
   const BoxRec& b = ctx->boxes[box];
-  const long n = b.n, hp = static_cast<long>(b.pitch());
-  // same layout and passes as one walker's spectrum in an evaluation
-  const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, 1);
-  const long parts = xs21::bins_parts(b.n, 1);
-  double* part = sl.part;
   double* outs = reinterpret_cast<double*>(ctx->ws + ctx->lay.outs);
-  const void* tw = tw_ptr(ctx, b.dtype);
-  HIPCHECK(ctx, xs21::launch_rows_r2c(b.dtype, b.n, field, sl.spec, sl.nyq, n * n, tw, kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, n, hp, n / 2, false, tw, kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, 1, n, n, true, tw, kNtab, ctx->stream));
-  HIPCHECK(ctx, xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, 1, parts,
-                                       reinterpret_cast<const int32_t*>(ctx->ws + b.off_bins_live),
-                                       static_cast<long>(b.bins_live.size()),
-                                       reinterpret_cast<const int8_t*>(ctx->ws + b.off_bintab), b.bintab.data(),
-                                       b.nbins, part, tw, kNtab, ctx->stream));
-  const double L3 = b.box * b.box * b.box;
-  HIPCHECK(ctx, xs21::launch_finalize(1, part, parts, b.nbins, nullptr, 0,
-                                      reinterpret_cast<const double*>(ctx->ws + b.off_counts),
-                                      L3 / std::pow(static_cast<double>(n), 6), 1.0, outs, b.nbins, b.nbins, nullptr,
-                                      0, ctx->stream));
+  HIPCHECK(ctx, power_spectrum_into(ctx, b, field, ctx->ws + ctx->lay.scratch, outs));
   HIPCHECK(ctx, hipMemcpyAsync(pk, outs, b.nbins * 8, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_power_spectrum_static(xs21_ctx* ctx, xs21_box box, const void* field, double* pk_dev) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (xs21_status s = check_box(ctx, box)) return s;
+  if (!field || !pk_dev) return fail(XS21_EINVAL, "null argument");
+  const BoxRec& b = ctx->boxes[box];
+  const size_t need = pk_scratch_bytes(b);
+  if (need > xs21::static_scratch_bytes())
+    return fail(XS21_EINVAL, "box of %d^3 (%s) needs %zu bytes of scratch; the static scratch holds %zu", b.n,
+                b.dtype == XS21_F64 ? "F64" : "F32", need, xs21::static_scratch_bytes());
+  unsigned char* scratch = static_cast<unsigned char*>(xs21::static_scratch(ctx->device));
+  if (!scratch) return fail(XS21_ESTATE, "static scratch address not set for device %d", ctx->device);
+  HIPCHECK(ctx, power_spectrum_into(ctx, b, field, scratch, pk_dev));
   return XS21_OK;
 }
 

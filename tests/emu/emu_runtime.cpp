@@ -257,3 +257,9 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
   return hipSuccess;
 }
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  if (!p || !symbol) return hipErrorInvalidValue;
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}

@@ -36,12 +36,15 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define __constant__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 
 typedef int hipError_t;
 enum {
   hipSuccess = 0,
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
+  hipErrorInvalidSymbol = 13,
   hipErrorNoDevice = 100,
   hipErrorLaunchFailure = 719
 };
@@ -199,4 +202,6 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipEventDestroy(hipEvent_t e);
+// device address of a __device__ variable: the host object itself here
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 }

@@ -18,9 +18,9 @@ ROOT = os.path.dirname(HERE)
 EMU = os.path.join(HERE, "emu")
 BIN = os.path.join(EMU, "_build", "xs21_emu")
 SRC = [os.path.join(ROOT, "paper_1501_06576_amd", "csrc", f)
-       for f in ("kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "api.cpp",
-                 "plan.cpp")]
-NHIP = 5   # leading SRC entries that are HIP sources (compiled as C++ here)
+       for f in ("kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "static_scratch.hip",
+                 "api.cpp", "plan.cpp")]
+NHIP = 6   # leading SRC entries that are HIP sources (compiled as C++ here)
 EXTRA = [os.path.join(EMU, "emu_runtime.cpp"), os.path.join(EMU, "driver.cpp")]
 
 
