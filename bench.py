@@ -99,6 +99,163 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------- rocprofv3 summaries
+
+def kernel_class(name: str):
+    """The library's kernel class of a kernel symbol (the classes of xs21_profile_read),
+    "probe" for the HBM probes, None for kernels outside the library."""
+    import re
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
+    rules = (("k_rows_r2c", "rows_r2c"), ("k_rows_c2r", "rows_c2r"), ("k_axis_bins", "axis_bins"),
+             ("k_ion", "ion"), ("k_finalize", "finalize"), ("k_probe", "probe"))
+    for pre, cls in rules:
+        if re.search(r"\b" + pre, n):
+            return cls
+    m = re.search(r"\bk_axis(_pipe)?<[^,]+, *\d+, *(-?1)", n)
+    if m:
+        return "axis_fwd" if m.group(2) == "-1" else "axis_inv"
+    if re.search(r"\bk_(plan|walker2|slot_tables)", n):
+        return "plan"
+    if re.search(r"\bk_", n) and "xs21" in name or re.search(r"\bk_(los_factor|chi2|lnprob|cast|stretch)", n):
+        return "other"
+    return None
+
+
+def _short(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
+    return n.replace("xs21::", "").replace("void ", "").strip()[:52]
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _counter_runs(directory):
+    """{counter: {dispatch: (kernel name, value)}} over every counter-collection CSV below `directory`."""
+    import glob
+    out = {}
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        for r in _csv_rows(f):
+            c = r.get("Counter_Name")
+            if not c:
+                continue
+            key = (f, r.get("Dispatch_Id"))
+            cur = out.setdefault(c, {}).get(key)
+            val = float(r["Counter_Value"])
+            out[c][key] = (r["Kernel_Name"], val + (cur[1] if cur else 0.0))
+    return out
+
+
+def summarize_profiles(directory: str, bench_json: str, workload: str, commands: list):
+    """Writes profiles/traffic.json, profiles/valu.json and their text tables from the
+    rocprofv3 counter runs under `directory` (FETCH_SIZE and WRITE_SIZE runs of
+    `bench.py --calibrate`, an SQ counter run), and profiles/kernels_<workload>.txt from
+    a --kernel-trace --stats run.  Per kernel symbol the median over its dispatches is
+    taken (the fiducial mock's single-walker launches are a minority)."""
+    import glob
+    import statistics
+    with open(bench_json) as fh:
+        bench = json.loads(fh.read().strip().splitlines()[-1])
+    cal = bench["calibration"]
+    runs = _counter_runs(directory)
+    tag = workload.replace("-", "")
+    src_hash = kernel_source_hash()
+    prof_dir = os.path.join(ROOT, "profiles")
+
+    def per_kernel(counter):
+        by = {}
+        for name, v in runs.get(counter, {}).values():
+            by.setdefault(name, []).append(v)
+        return by
+
+    fetch, write = per_kernel("FETCH_SIZE"), per_kernel("WRITE_SIZE")
+    if fetch and write:
+        def probe(d, kind):
+            vals = [v for n, vs in d.items() if f"k_probe_{kind}" in n for v in vs]
+            return statistics.median(vals) * 1024.0 if vals else None
+        # scale = bytes the probe moves / bytes the counter reports, per access pattern
+        scales = {"read": cal["read"] / probe(fetch, "read"), "tile": cal["tile"] / probe(fetch, "tile"),
+                  "copy_fetch": 0.5 * cal["copy"] / probe(fetch, "copy"),
+                  "write": cal["write"] / probe(write, "write"), "copy_write": 0.5 * cal["copy"] / probe(write, "copy")}
+        fs, ws = scales["read"], scales["write"]
+        kernels, lines = {}, []
+        for name in sorted(set(fetch) | set(write)):
+            cls = kernel_class(name)
+            if cls in (None, "probe"):
+                continue
+            f = statistics.median(fetch.get(name, [0.0])) * 1024.0 * fs
+            w = statistics.median(write.get(name, [0.0])) * 1024.0 * ws
+            lines.append(f"{_short(name):52s} {len(fetch.get(name, [])):5d} {f / 1e6:10.1f} {w / 1e6:10.1f} "
+                         f"{(f + w) / 1e6:12.1f}")
+            if cls not in kernels or f + w > kernels[cls]["bytes_per_launch"]:
+                kernels[cls] = {"bytes_per_launch": f + w, "fetch_bytes": f, "write_bytes": w, "kernel": _short(name)}
+        t = {"source_hash": src_hash, "workload": workload, "fetch_scale": fs, "write_scale": ws,
+             "scales_by_pattern": scales, "commands": [c for c in commands if "FETCH" in c or "WRITE" in c],
+             "kernels": kernels}
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(t, fh, indent=1)
+        with open(os.path.join(prof_dir, f"traffic_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 HBM traffic per dispatch (median over dispatches): {workload} workload\n")
+            for c in t["commands"]:
+                fh.write(f"# command: {c}\n")
+            fh.write("# calibration with the project's probes in the same runs (bytes moved / counter bytes):\n")
+            fh.write("#   " + ", ".join(f"{k} {v:.3f}" for k, v in scales.items()) + "\n")
+            fh.write(f"#   FETCH_SIZE scaled by {fs:.3f} (streaming read), WRITE_SIZE by {ws:.3f}\n")
+            fh.write(f"# kernel source hash: {src_hash}\n\n")
+            fh.write(f"{'kernel':52s} {'disp':>5s} {'fetch MB':>10s} {'write MB':>10s} {'total MB/disp':>12s}\n")
+            fh.write("\n".join(lines) + "\n")
+        log(f"wrote {TRAFFIC_FILE}")
+
+    sq = [c for c in runs if c.startswith("SQ_")]
+    if sq:
+        med = {c: {n: statistics.median(vs) for n, vs in per_kernel(c).items()} for c in sq}
+        names = sorted(set().union(*(m.keys() for m in med.values())))
+        kernels, lines = {}, []
+        for name in names:
+            cls = kernel_class(name)
+            if cls in (None, "probe"):
+                continue
+            row = {c: med[c].get(name, 0.0) for c in sq}
+            waves = row.get("SQ_WAVES", 0.0) or 1.0
+            valu = row.get("SQ_INSTS_VALU", 0.0)
+            lines.append(f"{_short(name):52s} " + " ".join(f"{row[c] / waves:10.0f}" for c in sq if c != "SQ_WAVES")
+                         + f" {waves:9.0f}")
+            if cls not in kernels or valu > kernels[cls]["valu_insts_per_launch"]:
+                kernels[cls] = {"valu_insts_per_launch": valu, "waves_per_launch": waves, "kernel": _short(name),
+                                "per_wave": {c: row[c] / waves for c in sq if c != "SQ_WAVES"}}
+        t = {"source_hash": src_hash, "workload": workload, "commands": [c for c in commands if "SQ_" in c],
+             "kernels": kernels}
+        with open(VALU_FILE, "w") as fh:
+            json.dump(t, fh, indent=1)
+        with open(os.path.join(prof_dir, f"sq_counters_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 SQ counters per wave (median over dispatches): {workload} workload\n")
+            for c in t["commands"]:
+                fh.write(f"# command: {c}\n")
+            fh.write(f"# kernel source hash: {src_hash}\n\n")
+            fh.write(f"{'kernel':52s} " + " ".join(f"{c[3:][:10]:>10s}" for c in sq if c != "SQ_WAVES")
+                     + f" {'waves':>9s}\n")
+            fh.write("\n".join(lines) + "\n")
+        log(f"wrote {VALU_FILE}")
+
+    stats = sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True))
+    if stats:
+        rows = _csv_rows(stats[-1])
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        with open(os.path.join(prof_dir, f"kernels_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 kernel statistics: {workload} workload\n")
+            for c in commands:
+                if "--kernel-trace" in c:
+                    fh.write(f"# command: {c}\n")
+            fh.write(f"# kernel source hash: {src_hash}\n\n")
+            fh.write(f"{'kernel':52s} {'calls':>6s} {'total ms':>10s} {'avg us':>10s} {'%':>6s}\n")
+            for r in rows:
+                fh.write(f"{_short(r['Name']):52s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                         f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}\n")
+        log(f"wrote kernels_{tag}.txt")
+
+
 def cpu_model() -> str:
     """The host CPU's model name (Linux), or "" where it cannot be read."""
     try:
@@ -158,17 +315,31 @@ def cell_radii(ctx, hs, specs, walkers):
     return tot
 
 
+def tuning_cache() -> str:
+    """The autotuner's JSON cache (XS21_TUNING_CACHE, else ~/.cache/xs21/tuning.json)."""
+    path = os.environ.get("XS21_TUNING_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "xs21",
+                                                                  "tuning.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    return path
+
+
 class Batch:
-    """A prepared context over one workload's boxes with a mock for the chi^2 epilogue."""
+    """A prepared context (on its own stream) over one workload's boxes with a mock for
+    the chi^2 epilogue."""
 
     def __init__(self, xs, torch, wl, amp, walkers, phys_kw=None, group=64):
         self.torch = torch
+        self.xs = xs
         self.wl = wl
         log(f"workload {wl.name}: generating {len(wl.boxes)} boxes")
         self.boxes = synth.workload_boxes(wl, amp)
         self.walkers = walkers
         self.nw = len(walkers)
-        self.ctx = xs.Context(0, phys=xs.physics(pk_amp=amp, **(phys_kw or {})))
+        # a stream of its own (a launch graph cannot be recorded on the null stream), made
+        # torch's current stream so that tensors and host copies are ordered with the library
+        self.stream = torch.cuda.Stream()
+        torch.cuda.set_stream(self.stream)
+        self.ctx = xs.Context(0, stream=self.stream, phys=xs.physics(pk_amp=amp, **(phys_kw or {})))
         self.hs = [self.ctx.add_box(d, s.box_mpc, s.z, s.n_bins) for d, s in zip(self.boxes, wl.boxes)]
         self.ctx.prepare(wl.storage, max_walkers=min(self.nw, group), max_plain_radii=40)
         self.nbmax = max(s.n_bins for s in wl.boxes)
@@ -204,10 +375,45 @@ class Batch:
         self.torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps
 
+    def autotune(self):
+        """Launch shapes for each grid size of the workload (autotuner, JSON cache), timed on
+        the workload's first walker group."""
+        out = {}
+        t0 = time.perf_counter()
+        for n in sorted({s.n for s in self.wl.boxes}):
+            hs = [h for h, s in zip(self.hs, self.wl.boxes) if s.n == n]
+            out[str(n)] = self.ctx.autotune(hs, self.walkers[:64], reps=2, cache_path=tuning_cache())
+        out["seconds"] = round(time.perf_counter() - t0, 2)
+        return out
+
+    def graph_steady(self, reps):
+        """The steady state as one launch graph: ln p (chi^2 against the mock) of the walkers
+        held on the device, planned and evaluated on the device, recorded once and launched
+        `reps` times; also the same call made directly.  Returns ms per batch of both."""
+        torch = self.torch
+        w = np.asarray(self.walkers, dtype=np.float64)
+        x = np.column_stack([w[:, 0], w[:, 1], np.log10(w[:, 2])])
+        spec = self.xs.sampler((5.0, 5.0, 4.0), (100.0, 20.0, 6.0))
+        xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+        lp = torch.empty(self.nw, dtype=torch.float64, device="cuda")
+        ms_direct = self.timed(lambda: self.ctx.mcmc_lnprob(self.hs, spec, xd, lp), reps)
+        ref = lp.clone()
+        self.ctx.capture_begin()
+        self.ctx.mcmc_lnprob(self.hs, spec, xd, lp)
+        g = self.ctx.capture_end()
+        ms_graph = self.timed(g.launch, reps)
+        same = bool(torch.equal(lp, ref))
+        g.close()
+        return {"ms_per_batch": round(ms_graph, 4), "walker_evals_per_s": round(self.nw / (ms_graph * 1e-3), 2),
+                "direct_ms_per_batch": round(ms_direct, 4), "replay_equals_direct": same,
+                "note": "ln p = -chi^2/2 of device-resident walkers, planned on the device, one graph launch per batch"}
+
     def close(self):
         self.ctx.close()
         del self.pk, self.xhi, self.chi2
         self.ctx = None
+        self.torch.cuda.synchronize()
+        self.torch.cuda.set_stream(self.torch.cuda.default_stream())
         self.torch.cuda.empty_cache()
 
 
@@ -267,11 +473,12 @@ def section_plain_configs(xs, torch, amp, reps):
     return out
 
 
-def section_workload(xs, torch, amp, name, reps, group=64):
+def section_workload(xs, torch, amp, name, reps, group=64, graph=False):
     """Full step and steady state of another workload, with its kernel table and roofline."""
     wl = synth.WORKLOADS[name]
     walkers = synth.workload_walkers(wl)
     b = Batch(xs, torch, wl, amp, walkers, group=group)
+    tuning = b.autotune()
     ms_step = b.timed(b.step, reps)
     b.ctx.profile(True)
     ms_steady = b.timed(b.steady, reps)
@@ -283,7 +490,10 @@ def section_workload(xs, torch, amp, name, reps, group=64):
            "steady_state": {"ms_per_batch": round(ms_steady, 3),
                             "walker_evals_per_s": round(b.nw / (ms_steady * 1e-3), 2),
                             "gcell_r_per_s": round(cellr / (ms_steady * 1e-3) / 1e9, 2)},
-           "kernels_steady": kernel_table(prof, reps), "roofline_steady": roofline(prof, reps, name)}
+           "kernels_steady": kernel_table(prof, reps), "roofline_steady": roofline(prof, reps, name),
+           "tuning": tuning}
+    if graph:
+        out["steady_state"]["graph"] = b.graph_steady(reps)
     b.close()
     return out
 
@@ -306,9 +516,21 @@ def main():
                     help="skip the shared-stage timing, the steady state at 256 and 1024 walkers and the probes")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (plain 64^3 / 128^3, uneven BF16 mix, 512^3)")
+    ap.add_argument("--no-autotune", action="store_true", help="run with the default launch shapes")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with the HBM probes once each (references for counter scaling)")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="no GPU work: write the profiles/ summaries from the rocprofv3 output under DIR")
+    ap.add_argument("--bench-json", help="with --summarize: the JSON line of the profiled --calibrate run")
+    ap.add_argument("--commands", help="with --summarize: file holding the profiling commands, one a line")
     args = ap.parse_args()
+    if args.summarize:
+        cmds = []
+        if args.commands:
+            with open(args.commands) as fh:
+                cmds = [c.strip() for c in fh if c.strip()]
+        summarize_profiles(args.summarize, args.bench_json, args.workload, cmds)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by walkers and "
               "boxes across GPUs, which this build does not run", file=sys.stderr)
@@ -325,6 +547,7 @@ def main():
     walkers = synth.workload_walkers(wl)
     b = Batch(xs, torch, wl, amp, walkers)
     ctx, hs, nw = b.ctx, b.hs, b.nw
+    tuning = None if args.no_autotune else b.autotune()
 
     for _ in range(args.warmup):
         b.step()
@@ -345,6 +568,8 @@ def main():
     # steady state: smoothed boxes resident, only the per-walker work
     log("timing steady state")
     ms_steady = b.timed(b.steady, args.steps, warmup=2)
+    log("timing the steady state as a launch graph")
+    graph = b.graph_steady(args.steps)
 
     shared_stage = walker_scaling = probes = None
     if not args.no_scaling:
@@ -409,7 +634,8 @@ def main():
         "gcell_r_per_s": round(cellR / (ms_step * 1e-3) / 1e9, 2),
         "steady_state": {"ms_per_batch": round(ms_steady, 4), "walker_evals_per_s": round(nw / (ms_steady * 1e-3), 2),
                          "gcell_r_per_s": round(cellR / (ms_steady * 1e-3) / 1e9, 2),
-                         "more_walkers": walker_scaling},
+                         "more_walkers": walker_scaling, "graph": graph},
+        "tuning": tuning,
         "shared_stage": shared_stage,
         "step_hbm": step_hbm,
         "plain_per_walker": None if ms_plain is None else
@@ -544,9 +770,9 @@ def main():
         log("plain workloads (64^3 FP64, 128^3 x 3 z FP32) with the oracle beside them")
         result["plain_configs"] = section_plain_configs(xs, torch, amp, max(2, args.steps // 2))
         log("uneven BF16 workload (128^3 / 256^3 x 3 z, 256 walkers)")
-        result["uneven_mix"] = section_workload(xs, torch, amp, "uneven-mix", max(2, args.steps // 3))
+        result["uneven_mix"] = section_workload(xs, torch, amp, "uneven-mix", max(2, args.steps // 3), graph=True)
         log("large workload (512^3 x 3 z, 1024 walkers)")
-        result["large_512"] = section_workload(xs, torch, amp, "large-512", 1)
+        result["large_512"] = section_workload(xs, torch, amp, "large-512", 1, graph=True)
 
     props = torch.cuda.get_device_properties(0)
     result["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
@@ -555,9 +781,10 @@ def main():
                         "l2_bytes": getattr(props, "L2_cache_size", None),
                         "memory_gib": round(props.total_memory / 2 ** 30, 1)}
     if args.calibrate:
+        # each probe launched twice (warm-up and one timed launch); bytes it moves per launch
         c = xs.Context(0, phys=xs.physics())
-        for kind in ("read", "write", "copy", "tile"):
-            c.probe_bandwidth(kind, (3800 << 20) + (64 << 10), reps=1)
+        result["calibration"] = {kind: c.probe_bandwidth(kind, (3800 << 20) + (64 << 10), reps=1)["bytes_per_launch"]
+                                 for kind in ("read", "write", "copy", "tile")}
         c.close()
         log("calibration probes done")
     print(json.dumps(result), flush=True)

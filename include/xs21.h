@@ -382,6 +382,68 @@ xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long lo
 xs21_status xs21_probe_bandwidth(xs21_ctx* ctx, int kind, void* buf, size_t bytes, int reps,
                                  double* gbps, double* bytes_per_launch);
 
+/* ---------------------------------------------------------------- launch shapes */
+
+/* Launch shapes of the batched evaluation for boxes of one grid size (0, or
+ * -1 for flag_test, selects the built-in default).  Results do not depend on
+ * them except through the order of floating-point sums (the flag test is
+ * exact either way). */
+typedef struct {
+  int32_t ion_blocks;   /* blocks of the ionisation pass, <= 16384 (default 8192, or n^2/2 if fewer) */
+  int32_t pipe_blocks;  /* blocks of the pipelined strided passes and smoothing rows (default 2048) */
+  int32_t bins_blocks;  /* blocks of one binning launch over a walker group (default 2048) */
+  int32_t flag_test;    /* FP32 boxes, constant efficiency: 1 sorted-threshold search per radius
+                           for the whole walker group, 0 one compare per walker and radius */
+  int32_t group;        /* walkers per ionisation launch, <= 64 and <= max_walkers (default min of both) */
+} xs21_tuning;
+
+/* Sets (t != NULL) or clears (t == NULL) the launch shapes used for boxes of
+ * n^3 cells.  EINVAL: n not a power of two in [8, 512], values out of range. */
+xs21_status xs21_set_tuning(xs21_ctx* ctx, int n, const xs21_tuning* t);
+
+/* The launch shapes set for n (zeros / -1 where the defaults apply). */
+xs21_status xs21_get_tuning(xs21_ctx* ctx, int n, xs21_tuning* t);
+
+/* Chooses launch shapes for the listed boxes (one grid size) by timing
+ * xs21_eval_batch of `walkers` on them with HIP events (best of `reps` runs
+ * after a warm-up per candidate; coordinate descent from the defaults over
+ * the flag test, the ionisation grid, the walker group, the pipelined grid and
+ * the binning grid; a candidate must win by more than 1 %), and sets them for
+ * that size.  With cache_path != NULL the choice is stored in that JSON file
+ * under the key "arch|n=N|dtype|storage|nr=N_R|g=G" (device architecture,
+ * grid size, box dtype, smoothed-box storage, ladder length, walker group),
+ * and a later call finds it there without timing (*from_cache = 1).  Outputs
+ * may be NULL: the chosen shapes, the best batch time (ms; from the cache
+ * when cached).  Synchronous; not allowed during graph capture. */
+xs21_status xs21_autotune(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers,
+                          int nw, int reps, const char* cache_path, xs21_tuning* chosen,
+                          double* best_ms, int* from_cache);
+
+/* ---------------------------------------------------------------- launch graphs */
+
+typedef struct xs21_graph xs21_graph;
+
+/* Records the device work of the following calls on the context stream into a
+ * launch graph instead of running it (the stream must be a created stream,
+ * not the null stream; kernel timing must be off).  Only calls whose work is
+ * all on the device may be recorded: xs21_mcmc_lnprob, xs21_mcmc_step,
+ * xs21_chi2, xs21_resmooth, xs21_smoothed, xs21_power_spectrum_static,
+ * xs21_erfc_f32.  The others return XS21_ESTATE while capturing.  Device
+ * buffers named by the recorded calls are read and written again, at the same
+ * addresses, every time the graph is launched: e.g. a recorded
+ * xs21_mcmc_step advances the chain by one step per launch with the uniforms
+ * the caller has placed in `u` by then. */
+xs21_status xs21_capture_begin(xs21_ctx* ctx);
+
+/* Ends the recording and instantiates the graph (*out). */
+xs21_status xs21_capture_end(xs21_ctx* ctx, xs21_graph** out);
+
+/* Launches a recorded graph on the context stream.  Asynchronous. */
+xs21_status xs21_graph_launch(xs21_ctx* ctx, const xs21_graph* g);
+
+/* Releases a graph.  NULL is accepted. */
+xs21_status xs21_graph_destroy(xs21_graph* g);
+
 /* ---------------------------------------------------------------- host planning */
 /* Pure host functions (no device, no context): the FP64 scalar planning the
  * kernels consume, exposed so it can be checked on its own. */

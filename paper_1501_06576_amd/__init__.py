@@ -59,6 +59,15 @@ def sampler(lo: Sequence[float], hi: Sequence[float], a: float = 2.0) -> Sampler
     return s
 
 
+class Tuning(ctypes.Structure):
+    """Launch shapes for one grid size (0 / -1: defaults); see xs21_tuning."""
+    _fields_ = [("ion_blocks", ctypes.c_int32), ("pipe_blocks", ctypes.c_int32), ("bins_blocks", ctypes.c_int32),
+                ("flag_test", ctypes.c_int32), ("group", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Walker2(ctypes.Structure):
     """Two-population parameter set (zeta0, R_mfp, T_feed, alpha, beta) of eq. (9)."""
     _fields_ = [("zeta0", ctypes.c_double), ("r_mfp", ctypes.c_double), ("t_feed", ctypes.c_double),
@@ -96,6 +105,14 @@ _SIGNATURES = {
     "xs21_resmooth": (_I, [_P, _I, _P]),
     "xs21_erfc_f32": (_I, [_P, _P, _P, ctypes.c_long]),
     "xs21_power_spectrum_static": (_I, [_P, _I, _P, _P]),
+    "xs21_set_tuning": (_I, [_P, _I, _P]),
+    "xs21_get_tuning": (_I, [_P, _I, _P]),
+    "xs21_autotune": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _I, ctypes.c_char_p, _P, _DP,
+                           ctypes.POINTER(ctypes.c_int)]),
+    "xs21_capture_begin": (_I, [_P]),
+    "xs21_capture_end": (_I, [_P, ctypes.POINTER(_P)]),
+    "xs21_graph_launch": (_I, [_P, _P]),
+    "xs21_graph_destroy": (_I, [_P]),
     "xs21_probe_bandwidth": (_I, [_P, _I, _P, ctypes.c_size_t, _I, _DP, _DP]),
     "xs21_set_mock": (_I, [_P, _I, _DP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "xs21_chi2": (_I, [_P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P]),
@@ -188,7 +205,12 @@ def _walkers_array(walkers, kind=None) -> Tuple[ctypes.Array, int]:
 
 
 class Context:
-    """One xs21 context on one GPU and one HIP stream (torch's current stream by default)."""
+    """One xs21 context on one GPU and one HIP stream (torch's current stream by default).
+
+    Device tensors passed in must be ready on the context's stream; tensors the
+    methods return are allocated on that stream and written there asynchronously:
+    read them on that stream (make it torch's current stream) or after
+    synchronising it."""
 
     def __init__(self, device: int = 0, stream=None, phys: Optional[Physics] = None):
         import torch  # device memory and streams only
@@ -202,6 +224,12 @@ class Context:
         self.boxes: List[dict] = []
         self.workspace = None
         self._keep = []
+
+    def _empty(self, shape, dtype):
+        """An output tensor allocated on the context's stream, so that the caching
+        allocator orders its reuse after the library's work on that stream."""
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(shape, dtype=dtype, device=self.device)
 
     def close(self):
         if self._ctx:
@@ -260,7 +288,7 @@ class Context:
         """Allocates the workspace (one torch uint8 tensor) and builds the resident smoothed boxes."""
         torch = self.torch
         nbytes = self.workspace_size(storage, max_walkers, max_plain_radii)
-        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ws = self._empty(nbytes + 256, torch.uint8)
         off = (-ws.data_ptr()) % 256
         self.workspace = ws
         _check(library().xs21_prepare(self._ctx, ctypes.c_void_p(ws.data_ptr() + off), nbytes, _DTYPES[storage],
@@ -280,14 +308,14 @@ class Context:
         warr, nw = _walkers_array(walkers, Walker)
         nbmax = max(self.boxes[b]["n_bins"] for b in boxes)
         if pk is None:
-            pk = torch.empty((nw, len(boxes), nbmax), dtype=torch.float64, device=self.device)
+            pk = self._empty((nw, len(boxes), nbmax), torch.float64)
         if xhi is None:
-            xhi = torch.empty((nw, len(boxes)), dtype=torch.float64, device=self.device)
+            xhi = self._empty((nw, len(boxes)), torch.float64)
         b = self.boxes[boxes[field_box]] if 0 <= field_box < len(boxes) else self.boxes[boxes[0]]
         n = b["n"]
         td = torch.float64 if b["dtype"] == F64 else torch.float32
-        fx = torch.empty((n, n, n), dtype=td, device=self.device)
-        fd = torch.empty((n, n, n), dtype=td, device=self.device)
+        fx = self._empty((n, n, n), td)
+        fd = self._empty((n, n, n), td)
         _check(library().xs21_eval_batch_fields(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()),
                                                 ctypes.c_void_p(xhi.data_ptr()), int(field_walker), int(field_box),
                                                 ctypes.c_void_p(fx.data_ptr()), ctypes.c_void_p(fd.data_ptr())))
@@ -303,9 +331,9 @@ class Context:
         warr, nw = _walkers_array(walkers, kind)
         nbmax = max(self.boxes[b]["n_bins"] for b in boxes)
         if pk is None:
-            pk = torch.empty((nw, len(boxes), nbmax), dtype=torch.float64, device=self.device)
+            pk = self._empty((nw, len(boxes), nbmax), torch.float64)
         if xhi is None:
-            xhi = torch.empty((nw, len(boxes)), dtype=torch.float64, device=self.device)
+            xhi = self._empty((nw, len(boxes)), torch.float64)
         _check(fn(self._ctx, bx, len(boxes), warr, nw, ctypes.c_void_p(pk.data_ptr()), ctypes.c_void_p(xhi.data_ptr())))
         return pk, xhi
 
@@ -342,7 +370,7 @@ class Context:
         f64 = self.torch.float64
         self._dev(x, (nw, spec.dim), f64, "x")
         if lp is None:
-            lp = self.torch.empty(nw, dtype=f64, device=self.device)
+            lp = self._empty(nw, f64)
         self._dev(lp, (nw,), f64, "lp")
         _check(library().xs21_mcmc_lnprob(self._ctx, bx, len(boxes), ctypes.byref(spec),
                                           ctypes.c_void_p(x.data_ptr()), nw, ctypes.c_void_p(lp.data_ptr())))
@@ -377,8 +405,8 @@ class Context:
         b = self.boxes[box]
         n = b["n"]
         td = torch.float64 if b["dtype"] == F64 else torch.float32
-        x = torch.empty((n, n, n), dtype=td, device=self.device)
-        d = torch.empty((n, n, n), dtype=td, device=self.device)
+        x = self._empty((n, n, n), td)
+        d = self._empty((n, n, n), td)
         _check(fn(self._ctx, box, ctypes.byref(w), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d.data_ptr())))
         return x, d
 
@@ -387,7 +415,7 @@ class Context:
         b = self.boxes[box]
         n = b["n"]
         td = torch.float64 if b["dtype"] == F64 else torch.float32
-        out = torch.empty((n, n, n), dtype=td, device=self.device)
+        out = self._empty((n, n, n), td)
         _check(library().xs21_smoothed(self._ctx, box, index, ctypes.c_void_p(out.data_ptr())))
         return out
 
@@ -401,7 +429,7 @@ class Context:
     def probe_bandwidth(self, kind: str, nbytes: int = 1 << 30, reps: int = 5) -> dict:
         """HBM probe ("read", "write", "copy", "tile"): GB/s of bytes read + written per launch."""
         k = {"read": 0, "write": 1, "copy": 2, "tile": 3}[kind]
-        buf = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        buf = self._empty(nbytes + 256, self.torch.uint8)
         off = (-buf.data_ptr()) % 256
         g = ctypes.c_double()
         m = ctypes.c_double()
@@ -415,10 +443,46 @@ class Context:
         t = x.contiguous()
         if t.dtype != self.torch.float32 or not t.is_cuda:
             raise ValueError("erfc_f32 needs a float32 device tensor")
-        y = self.torch.empty_like(t)
+        y = self._empty(t.shape, t.dtype)
         _check(library().xs21_erfc_f32(self._ctx, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                        t.numel()))
         return y
+
+    def set_tuning(self, n: int, **shapes):
+        """Launch shapes for boxes of n^3 cells (keys of Tuning; none given: back to defaults)."""
+        if not shapes:
+            _check(library().xs21_set_tuning(self._ctx, n, None))
+            return
+        t = Tuning(0, 0, 0, -1, 0)
+        for k, v in shapes.items():
+            setattr(t, k, int(v))
+        _check(library().xs21_set_tuning(self._ctx, n, ctypes.byref(t)))
+
+    def get_tuning(self, n: int) -> dict:
+        t = Tuning()
+        _check(library().xs21_get_tuning(self._ctx, n, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, boxes: Sequence[int], walkers, reps: int = 3, cache_path: Optional[str] = None) -> dict:
+        """Times candidate launch shapes on eval_batch(boxes, walkers) and sets the best; with a
+        cache path, reuses / stores the choice there."""
+        bx = (ctypes.c_int32 * len(boxes))(*boxes)
+        warr, nw = _walkers_array(walkers, Walker)
+        t = Tuning()
+        ms = ctypes.c_double()
+        cached = ctypes.c_int()
+        _check(library().xs21_autotune(self._ctx, bx, len(boxes), warr, nw, reps,
+                                       None if cache_path is None else cache_path.encode(), ctypes.byref(t),
+                                       ctypes.byref(ms), ctypes.byref(cached)))
+        return {"tuning": t.as_dict(), "best_ms": ms.value, "from_cache": bool(cached.value)}
+
+    def capture_begin(self):
+        _check(library().xs21_capture_begin(self._ctx))
+
+    def capture_end(self) -> "Graph":
+        g = ctypes.c_void_p()
+        _check(library().xs21_capture_end(self._ctx, ctypes.byref(g)))
+        return Graph(self, g)
 
     def power_spectrum_static(self, box: int, field, pk=None):
         """P(k) of a device field through the allocation-free entry point (static device
@@ -426,7 +490,7 @@ class Context:
         b = self.boxes[box]
         f = field.contiguous()
         if pk is None:
-            pk = self.torch.empty(b["n_bins"], dtype=self.torch.float64, device=self.device)
+            pk = self._empty(b["n_bins"], self.torch.float64)
         self._dev(pk, (b["n_bins"],), self.torch.float64, "pk")
         _check(library().xs21_power_spectrum_static(self._ctx, box, ctypes.c_void_p(f.data_ptr()),
                                                     ctypes.c_void_p(pk.data_ptr())))
@@ -451,7 +515,7 @@ class Context:
         bx = (ctypes.c_int32 * len(boxes))(*boxes)
         nw = pk.shape[0]
         if out is None:
-            out = self.torch.empty(nw, dtype=self.torch.float64, device=self.device)
+            out = self._empty(nw, self.torch.float64)
         _check(library().xs21_chi2(self._ctx, bx, len(boxes), ctypes.c_void_p(pk.data_ptr()), nw,
                                    ctypes.c_void_p(out.data_ptr())))
         return out
@@ -479,3 +543,25 @@ class Context:
 
     def sync(self):
         _check(library().xs21_sync(self._ctx))
+
+
+class Graph:
+    """A launch graph recorded on a context's stream (xs21_capture_begin / _end)."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self._g = handle
+
+    def launch(self):
+        _check(library().xs21_graph_launch(self.ctx._ctx, self._g))
+
+    def close(self):
+        if self._g:
+            library().xs21_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -129,8 +130,21 @@ struct Layout {
 
 }  // namespace
 
+// Launch shapes of one box size (0 / -1: the launchers' defaults).
+struct Tune {
+  int ion_blocks = 0, pipe_blocks = 0, bins_blocks = 0, flag_test = -1, group = 0;
+};
+
+struct xs21_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
 struct xs21_ctx {
   int device = 0;
+  std::map<int, Tune> tune;   // per grid size n
+  bool capturing = false;     // inside xs21_capture_begin / xs21_capture_end
   hipStream_t stream = nullptr;
   xs21_physics phys{};
   std::vector<BoxRec> boxes;
@@ -186,6 +200,24 @@ xs21_status check_ctx(xs21_ctx* c) {
 xs21_status check_box(xs21_ctx* c, xs21_box b) {
   if (b < 0 || b >= static_cast<int>(c->boxes.size())) return fail(XS21_EINVAL, "unknown box handle %d", b);
   return XS21_OK;
+}
+
+// Entry points that synchronise with the host or upload host data cannot be
+// recorded into a graph.
+xs21_status no_capture(xs21_ctx* c, const char* what) {
+  if (c->capturing) return fail(XS21_ESTATE, "%s is not allowed during graph capture", what);
+  return XS21_OK;
+}
+
+Tune tune_of(const xs21_ctx* c, int n) {
+  const auto it = c->tune.find(n);
+  return it == c->tune.end() ? Tune{} : it->second;
+}
+
+// Walkers per ionisation launch on boxes of size n.
+int group_of(const xs21_ctx* c, int n) {
+  const int g = tune_of(c, n).group;
+  return g > 0 ? std::min(g, c->group) : c->group;
 }
 
 hipEvent_t pooled_event(xs21_ctx* c) {
@@ -258,7 +290,7 @@ size_t eval_scratch(const BoxRec& b, int group) {
   const long tiles = xs21::bins_tiles(b.n);
   return align_up(group * b.spec_bytes()) + align_up(group * nyq_bytes(b)) +
          align_up(static_cast<size_t>(group) * tiles * b.nbins * 8) +
-         align_up(static_cast<size_t>(group) * xs21::ion_grid(b.n) * 8);
+         align_up(static_cast<size_t>(group) * xs21::ion_grid_max(b.n) * 8);
 }
 
 size_t plain_scratch(const BoxRec& b, int max_plain) {
@@ -481,7 +513,7 @@ hipError_t smooth_batch(xs21_ctx* c, hipStream_t st, const BoxRec& b, const void
   const double scale = 1.0 / (static_cast<double>(n) * n * n);
   return timed(c, st, XS21_K_ROWS_C2R, xb, [&] {
     return xs21::launch_rows_c2r(b.dtype, storage, b.n, tmp, out, n * n, scale, cut_dev, cnt, sstride,
-                                 static_cast<long>(b.cells()), tw, kNtab, st);
+                                 static_cast<long>(b.cells()), tw, kNtab, st, tune_of(c, b.n).pipe_blocks);
   });
 }
 
@@ -581,7 +613,8 @@ hipError_t ion_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
       [&] {
         return xs21::launch_ion(b.dtype, storage, b.n, dR, c->ws + b.off_od, nr, wc, thr, zt, count, tb,
                                 c->phys.delta_c, sl.spec, sl.nyq, sl.xpart, tw_ptr(c, b.dtype), kNtab, st,
-                                field_walker, fx, fd, c->ws + c->lay.slot_tab);
+                                field_walker, fx, fd, c->ws + c->lay.slot_tab, tune_of(c, b.n).ion_blocks,
+                                tune_of(c, b.n).flag_test);
       },
       ion_ops);
 }
@@ -594,17 +627,20 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   const long n = b.n, h = static_cast<long>(b.half()), hp = static_cast<long>(b.pitch());
   const double rs = static_cast<double>(real_size(b.dtype));
   const double cells = static_cast<double>(b.cells()), modes = static_cast<double>(n * n * h);
-  const long parts = xs21::bins_parts(b.n, count);
+  const Tune tu = tune_of(c, b.n);
+  const long parts = xs21::bins_parts(b.n, count, tu.bins_blocks);
+  const int ion_blocks = xs21::ion_grid(b.n, tu.ion_blocks);   // the x_HI partials of the ionisation launch
   const void* tw = tw_ptr(c, b.dtype);
   // y pass of the kx < N/2 columns, then of the Nyquist planes; only modes
   // with ny^2 + kx^2 <= (N/2)^2 are stored (no other mode is binned)
   const double ntl = static_cast<double>(b.bins_live.size());
   hipError_t e = timed(c, st, XS21_K_AXIS_FWD, count * n * (n * (n / 2) + b.live_yx) * 2 * rs, [&] {
-    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, count * n, hp, n / 2, false, tw, kNtab, st);
+    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.spec, count * n, hp, n / 2, false, tw, kNtab, st,
+                                      tu.pipe_blocks);
   });
   if (e != hipSuccess) return e;
   e = timed(c, st, XS21_K_AXIS_FWD, count * n * (n + 1) * 2 * rs, [&] {
-    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, count, n, n, true, tw, kNtab, st);
+    return xs21::launch_axis_fwd_disk(b.dtype, b.n, sl.nyq, count, n, n, true, tw, kNtab, st, tu.pipe_blocks);
   });
   if (e != hipSuccess) return e;
   // the binning pass reads the live tiles (TI columns x N values each)
@@ -618,9 +654,9 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   if (e != hipSuccess) return e;
   const double L3 = b.box * b.box * b.box;
   const double n6 = std::pow(static_cast<double>(n), 6);
-  const double pbytes = static_cast<double>(count) * (parts * b.nbins + xs21::ion_grid(b.n)) * 8;
+  const double pbytes = static_cast<double>(count) * (parts * b.nbins + ion_blocks) * 8;
   return timed(c, st, XS21_K_FINALIZE, pbytes, [&] {
-    return xs21::launch_finalize(count, sl.part, parts, b.nbins, sl.xpart, xs21::ion_grid(b.n),
+    return xs21::launch_finalize(count, sl.part, parts, b.nbins, sl.xpart, ion_blocks,
                                  reinterpret_cast<const double*>(c->ws + b.off_counts), L3 / n6, 1.0 / cells, pk,
                                  pk_stride, nbins_out, xhi, xhi_stride, st);
   });
@@ -706,6 +742,7 @@ xs21_status xs21_sync(xs21_ctx* ctx) {
   g_error.clear();
   xs21_status s = check_ctx(ctx);
   if (s) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_sync")) return s_;
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   return XS21_OK;
 }
@@ -840,6 +877,7 @@ xs21_status xs21_prepare(xs21_ctx* ctx, void* workspace, size_t bytes, xs21_dtyp
                          int max_plain_radii) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_prepare")) return s_;
   if (ctx->prepared) return fail(XS21_ESTATE, "already prepared");
   size_t need = 0;
   if (xs21_status s = xs21_workspace_size(ctx, storage, max_walkers, max_plain_radii, &need)) return s;
@@ -910,6 +948,7 @@ xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
                             int field_box = -1, void* fx = nullptr, void* fd = nullptr) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "evaluation with host-planned walkers (xs21_eval_batch)")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (!boxes || nb < 1 || !(w1 || w2) || nw < 1) return fail(XS21_EINVAL, "empty batch");
   if (nb > static_cast<int>(ctx->boxes.size())) return fail(XS21_EINVAL, "more listed boxes than registered");
@@ -976,8 +1015,9 @@ xs21_status eval_batch_impl(xs21_ctx* ctx, const xs21_box* boxes, int nb, const 
                                     ctx->phys.delta_c, st);
         }));
       }
-      for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
-        const int g = std::min(ctx->group, cnt - g0);
+      const int G = group_of(ctx, b.n);
+      for (int g0 = 0; g0 < cnt; g0 += G) {
+        const int g = std::min(G, cnt - g0);
         const long wg = w0 + g0;
         double used = 0;
         for (int k = 0; k < g; ++k) used += b.nr() - first_radius(b, r_mfp(wg + k));
@@ -1064,8 +1104,9 @@ hipError_t eval_dev(xs21_ctx* ctx, const xs21_box* boxes, int nb, int d, const d
       });
     }
     if (e != hipSuccess) return e;
-    for (int g0 = 0; g0 < cnt; g0 += ctx->group) {
-      const int g = std::min(ctx->group, cnt - g0);
+    const int G = group_of(ctx, b.n);
+    for (int g0 = 0; g0 < cnt; g0 += G) {
+      const int g = std::min(G, cnt - g0);
       const EvalSlot sl = eval_slot(b, ctx->ws + ctx->lay.scratch, g);
       e = ion_stage(ctx, st, b, sl, ctx->ws + b.off_dR, b.storage, b.nr(), wc + g0 * b.wc_size(),
                     thr + static_cast<size_t>(g0) * thr_w,
@@ -1185,6 +1226,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
                       void* x_hi, void* dtb, double* pk, double* k_mean, double* counts, double* xhi_mean) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_eval")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!walker || !xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
@@ -1258,6 +1300,7 @@ xs21_status xs21_eval(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, co
 xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* walker, void* x_hi, void* dtb) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_materialize")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!walker || !xs21::plan::valid_walker(*walker)) return fail(XS21_EINVAL, "invalid walker");
@@ -1280,6 +1323,7 @@ xs21_status xs21_materialize(xs21_ctx* ctx, xs21_box box, const xs21_walker* wal
 xs21_status xs21_materialize2(xs21_ctx* ctx, xs21_box box, const xs21_walker2* walker, void* x_hi, void* dtb) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_materialize2")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!walker || !xs21::plan::valid_walker2(*walker)) return fail(XS21_EINVAL, "invalid walker");
@@ -1363,6 +1407,7 @@ extern "C" {
 xs21_status xs21_power_spectrum(xs21_ctx* ctx, xs21_box box, const void* field, double* pk) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_power_spectrum")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!field || !pk) return fail(XS21_EINVAL, "null argument");
@@ -1395,6 +1440,7 @@ xs21_status xs21_probe_bandwidth(xs21_ctx* ctx, int kind, void* buf, size_t byte
                                  double* bytes_per_launch) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_probe_bandwidth")) return s_;
   if (kind < 0 || kind > 3) return fail(XS21_EINVAL, "unknown probe kind %d", kind);
   if (!buf || reps < 1 || !gbps) return fail(XS21_EINVAL, "null or empty argument");
   if (reinterpret_cast<uintptr_t>(buf) % kAlign) return fail(XS21_EINVAL, "probe buffer not 256-byte aligned");
@@ -1432,6 +1478,7 @@ xs21_status xs21_set_mock(xs21_ctx* ctx, xs21_box box, const double* delta2_mock
                           double model_err, double k_lo, double k_hi) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_set_mock")) return s_;
   if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
   if (xs21_status s = check_box(ctx, box)) return s;
   if (!delta2_mock) return fail(XS21_EINVAL, "null mock");
@@ -1496,6 +1543,7 @@ xs21_status xs21_resmooth(xs21_ctx* ctx, xs21_box box, const void* new_delta) {
 xs21_status xs21_profile(xs21_ctx* ctx, int enable) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_profile")) return s_;
   if (enable) {
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     for (auto& r : ctx->pending) {
@@ -1514,6 +1562,7 @@ xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long lo
                               double* ops) {
   g_error.clear();
   if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s_ = no_capture(ctx, "xs21_profile_read")) return s_;
   if (kind < 0 || kind >= XS21_K_COUNT) return fail(XS21_EINVAL, "unknown kernel class %d", kind);
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   for (auto& r : ctx->pending) {
@@ -1531,6 +1580,306 @@ xs21_status xs21_profile_read(xs21_ctx* ctx, int kind, double* total_ms, long lo
   if (launches) *launches = ctx->launches[kind];
   if (bytes) *bytes = ctx->tot_bytes[kind];
   if (ops) *ops = ctx->tot_ops[kind];
+  return XS21_OK;
+}
+
+// ------------------------------------------------------------ launch shapes
+
+}  // extern "C"
+
+namespace {
+
+bool valid_tuning(const xs21_tuning& t) {
+  return t.ion_blocks >= 0 && t.ion_blocks <= 16384 && t.pipe_blocks >= 0 && t.pipe_blocks <= 65535 &&
+         t.bins_blocks >= 0 && t.bins_blocks <= 65535 && t.flag_test >= -1 && t.flag_test <= 1 && t.group >= 0 &&
+         t.group <= xs21::max_group();
+}
+
+Tune to_tune(const xs21_tuning& t) {
+  Tune u;
+  u.ion_blocks = t.ion_blocks;
+  u.pipe_blocks = t.pipe_blocks;
+  u.bins_blocks = t.bins_blocks;
+  u.flag_test = t.flag_test;
+  u.group = t.group;
+  return u;
+}
+
+xs21_tuning from_tune(const Tune& u) {
+  xs21_tuning t;
+  t.ion_blocks = u.ion_blocks;
+  t.pipe_blocks = u.pipe_blocks;
+  t.bins_blocks = u.bins_blocks;
+  t.flag_test = u.flag_test;
+  t.group = u.group;
+  return t;
+}
+
+const char* dtype_name(int d) { return d == xs21::kF64 ? "f64" : (d == xs21::kBF16 ? "bf16" : "f32"); }
+
+// Entries of a tuning cache file: one line per key, "key": {...}.
+std::map<std::string, std::string> read_cache(const char* path) {
+  std::map<std::string, std::string> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* q0 = std::strchr(line, '"');
+    if (!q0) continue;
+    const char* q1 = std::strchr(q0 + 1, '"');
+    const char* brace = q1 ? std::strchr(q1, '{') : nullptr;
+    const char* end = brace ? std::strchr(brace, '}') : nullptr;
+    if (!end) continue;
+    out[std::string(q0 + 1, q1)] = std::string(brace, end + 1);
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool parse_entry(const std::string& obj, Tune* t, double* ms) {
+  const auto field = [&](const char* name, double* v) {
+    const std::string key = std::string("\"") + name + "\":";
+    const size_t at = obj.find(key);
+    if (at == std::string::npos) return false;
+    return std::sscanf(obj.c_str() + at + key.size(), "%lf", v) == 1;
+  };
+  double a, b, c, d, e, m = -1.0;
+  if (!(field("ion_blocks", &a) && field("pipe_blocks", &b) && field("bins_blocks", &c) && field("flag_test", &d) &&
+        field("group", &e)))
+    return false;
+  (void)field("ms", &m);
+  t->ion_blocks = static_cast<int>(a);
+  t->pipe_blocks = static_cast<int>(b);
+  t->bins_blocks = static_cast<int>(c);
+  t->flag_test = static_cast<int>(d);
+  t->group = static_cast<int>(e);
+  *ms = m;
+  return true;
+}
+
+bool write_cache(const char* path, const std::map<std::string, std::string>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : entries)
+    std::fprintf(f, "\"%s\": %s%s\n", kv.first.c_str(), kv.second.c_str(), ++i < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+xs21_status xs21_set_tuning(xs21_ctx* ctx, int n, const xs21_tuning* t) {
+  g_error.clear();
+  if (!ctx) return fail(XS21_EINVAL, "null context");
+  if (!pow2_in_range(n)) return fail(XS21_EINVAL, "n = %d is not a power of two in [8, 512]", n);
+  if (!t) {
+    ctx->tune.erase(n);
+    return XS21_OK;
+  }
+  if (!valid_tuning(*t)) return fail(XS21_EINVAL, "tuning values out of range");
+  ctx->tune[n] = to_tune(*t);
+  return XS21_OK;
+}
+
+xs21_status xs21_get_tuning(xs21_ctx* ctx, int n, xs21_tuning* t) {
+  g_error.clear();
+  if (!ctx || !t) return fail(XS21_EINVAL, "null argument");
+  if (!pow2_in_range(n)) return fail(XS21_EINVAL, "n = %d is not a power of two in [8, 512]", n);
+  *t = from_tune(tune_of(ctx, n));
+  return XS21_OK;
+}
+
+xs21_status xs21_autotune(xs21_ctx* ctx, const xs21_box* boxes, int nb, const xs21_walker* walkers, int nw, int reps,
+                          const char* cache_path, xs21_tuning* chosen, double* best_ms, int* from_cache) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (xs21_status s = no_capture(ctx, "xs21_autotune")) return s;
+  if (!ctx->prepared) return fail(XS21_ESTATE, "xs21_prepare has not run");
+  if (!boxes || nb < 1 || !walkers || nw < 1 || reps < 1) return fail(XS21_EINVAL, "empty or null argument");
+  int n = 0, nr = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (xs21_status s = check_box(ctx, boxes[i])) return s;
+    const BoxRec& b = ctx->boxes[boxes[i]];
+    if (i && b.n != n) return fail(XS21_EINVAL, "boxes tuned together must share their grid size");
+    n = b.n;
+    nr = std::max(nr, b.nr());
+  }
+  const BoxRec& b0 = ctx->boxes[boxes[0]];
+  hipDeviceProp_t prop;
+  HIPCHECK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  char key[256];
+  std::snprintf(key, sizeof key, "%s|n=%d|%s|%s|nr=%d|g=%d", arch.c_str(), n, dtype_name(b0.dtype),
+                dtype_name(b0.storage), nr, std::min(nw, ctx->group));
+  std::map<std::string, std::string> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    const auto it = cache.find(key);
+    Tune t;
+    double ms = -1.0;
+    if (it != cache.end() && parse_entry(it->second, &t, &ms) && valid_tuning(from_tune(t))) {
+      ctx->tune[n] = t;
+      if (chosen) *chosen = from_tune(t);
+      if (best_ms) *best_ms = ms;
+      if (from_cache) *from_cache = 1;
+      return XS21_OK;
+    }
+  }
+  // time eval_batch over the listed boxes for one setting (best of reps, after a warm-up)
+  hipEvent_t ea = pooled_event(ctx), eb = pooled_event(ctx);
+  if (!ea || !eb) return fail(XS21_EDEVICE, "event creation failed");
+  xs21_status err = XS21_OK;
+  const auto time_cfg = [&](const Tune& t) {
+    ctx->tune[n] = t;
+    double best = 1e300;
+    for (int r = 0; r <= reps && err == XS21_OK; ++r) {
+      hipError_t e = hipEventRecord(ea, ctx->stream);
+      if (e == hipSuccess) err = eval_batch_impl(ctx, boxes, nb, walkers, nullptr, nw, nullptr, nullptr);
+      if (err != XS21_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(eb, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(eb);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+      if (e != hipSuccess) {
+        err = hip_fail(ctx, e, "autotune timing");
+        break;
+      }
+      if (r > 0) best = std::min(best, static_cast<double>(ms));
+    }
+    return best;
+  };
+  // coordinate descent from the defaults, one knob at a time; a change must
+  // win by more than 1 % (timing noise)
+  const int cells2 = n * n / 2;
+  Tune best;
+  best.ion_blocks = xs21::ion_grid(n);
+  best.pipe_blocks = 2048;
+  best.bins_blocks = 2048;
+  best.flag_test = b0.dtype == xs21::kF32 ? 1 : 0;
+  best.group = ctx->group;
+  double best_t = time_cfg(best);
+  const auto trial = [&](Tune t) {
+    if (err != XS21_OK) return;
+    const double ms = time_cfg(t);
+    if (err == XS21_OK && ms < 0.99 * best_t) {
+      best = t;
+      best_t = ms;
+    }
+  };
+  if (b0.dtype == xs21::kF32) {
+    Tune t = best;
+    t.flag_test = 0;
+    trial(t);
+  }
+  for (int v : {2048, 4096, 8192, 16384}) {
+    if (v == best.ion_blocks || v > cells2) continue;
+    Tune t = best;
+    t.ion_blocks = v;
+    trial(t);
+  }
+  for (int v : {32, 48}) {
+    if (v >= ctx->group || v >= nw) continue;
+    Tune t = best;
+    t.group = v;
+    trial(t);
+  }
+  for (int v : {1024, 4096}) {
+    Tune t = best;
+    t.pipe_blocks = v;
+    trial(t);
+  }
+  for (int v : {1024, 4096, 8192}) {
+    Tune t = best;
+    t.bins_blocks = v;
+    trial(t);
+  }
+  ctx->pool.push_back(ea);
+  ctx->pool.push_back(eb);
+  if (err != XS21_OK) return err;
+  ctx->tune[n] = best;
+  if (chosen) *chosen = from_tune(best);
+  if (best_ms) *best_ms = best_t;
+  if (from_cache) *from_cache = 0;
+  if (cache_path) {
+    char obj[256];
+    std::snprintf(obj, sizeof obj,
+                  "{\"ion_blocks\": %d, \"pipe_blocks\": %d, \"bins_blocks\": %d, \"flag_test\": %d, "
+                  "\"group\": %d, \"ms\": %.4f}",
+                  best.ion_blocks, best.pipe_blocks, best.bins_blocks, best.flag_test, best.group, best_t);
+    cache[key] = obj;
+    if (!write_cache(cache_path, cache)) return fail(XS21_EINVAL, "cannot write the tuning cache %s", cache_path);
+  }
+  return XS21_OK;
+}
+
+// ------------------------------------------------------------ graph capture
+
+xs21_status xs21_capture_begin(xs21_ctx* ctx) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (ctx->capturing) return fail(XS21_ESTATE, "already capturing");
+  if (!ctx->stream) return fail(XS21_EINVAL, "graph capture needs a context on a created stream, not the null stream");
+  if (ctx->prof) return fail(XS21_ESTATE, "kernel timing (xs21_profile) is on");
+  if (ctx->upload_pending) {
+    HIPCHECK(ctx, hipEventSynchronize(ctx->upload_done));
+    ctx->upload_pending = false;
+  }
+  HIPCHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  return XS21_OK;
+}
+
+xs21_status xs21_capture_end(xs21_ctx* ctx, xs21_graph** out) {
+  g_error.clear();
+  if (!ctx || !out) return fail(XS21_EINVAL, "null argument");
+  if (!ctx->capturing) return fail(XS21_ESTATE, "not capturing");
+  *out = nullptr;
+  (void)hipSetDevice(ctx->device);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+  ctx->capturing = false;
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+  auto* gr = new (std::nothrow) xs21_graph;
+  if (!gr) {
+    (void)hipGraphDestroy(g);
+    return fail(XS21_ENOMEM, "host allocation failed");
+  }
+  gr->graph = g;
+  gr->device = ctx->device;
+  const hipError_t e2 = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete gr;
+    return hip_fail(ctx, e2, "hipGraphInstantiate");
+  }
+  *out = gr;
+  return XS21_OK;
+}
+
+xs21_status xs21_graph_launch(xs21_ctx* ctx, const xs21_graph* g) {
+  g_error.clear();
+  if (xs21_status s = check_ctx(ctx)) return s;
+  if (!g) return fail(XS21_EINVAL, "null graph");
+  if (ctx->capturing) return fail(XS21_ESTATE, "cannot launch a graph while capturing");
+  if (g->device != ctx->device) return fail(XS21_EINVAL, "graph was captured on device %d", g->device);
+  HIPCHECK(ctx, hipGraphLaunch(g->exec, ctx->stream));
+  return XS21_OK;
+}
+
+xs21_status xs21_graph_destroy(xs21_graph* g) {
+  g_error.clear();
+  if (!g) return XS21_OK;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return XS21_OK;
 }
 

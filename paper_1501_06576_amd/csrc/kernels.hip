@@ -510,7 +510,14 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
   // this thread's slot of bin b0 + bb sits at slot[(brow + bb) TI + cc]
   const int brow = bs.base[j] - (bs.lo[j] - b0);
   constexpr int NB2 = (N / 2) * (N / 2) + 1;  // |n|^2 > (N/2)^2 is never binned
+  // The next tile's values and the bins of this thread's outputs of it are
+  // loaded together, one tile ahead: the wait for a tile's data at the top of
+  // the loop then also covers its bins, and no load issued for the next tile
+  // is waited on before the loop comes round.  Bins are loaded
+  // unconditionally (entry 0, the dropped DC mode, stands in for modes that
+  // are not binned).
   cplx<T> pre[L];
+  int nbin[M];
   const cplx<T>* nq = nyq + spec * N * N;
   const auto load = [&](long tile) {
     int ky, kx;
@@ -526,6 +533,16 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
       const cplx<T> v = base[k * step];
       pre[k] = live ? v : cplx<T>{T(0), T(0)};
     }
+    // this thread's outputs of the tile: column (ky, kx), kz = j M .. j M + M - 1
+    const int ny = ky < N / 2 ? ky : ky - N;
+    const int cyx = ny * ny + kx * kx;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int kz = j * M + m;
+      const int nz = kz < N / 2 ? kz : kz - N;
+      const int n2 = nz * nz + cyx;
+      nbin[m] = bintab[(live && n2 < NB2) ? n2 : 0];
+    }
   };
   __syncthreads();  // slots cleared before any thread adds to them
   if (first < ntiles) load(tiles[first]);
@@ -533,24 +550,13 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* _
     const long tile = tiles[e];
 #pragma unroll
     for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
-    __syncthreads();
-    if (e + parts < ntiles) load(tiles[e + parts]);
-    // this thread's outputs: column (ky, kx), kz = j M .. j M + M - 1.  Their
-    // bins are loaded before the FFT, unconditionally (entry 0, the dropped DC
-    // mode, stands in for modes that are not binned), so that the loads
-    // overlap the transform.
-    int ky, kx;
-    BT::column(tile, cc, ky, kx);
-    const int ny = ky < N / 2 ? ky : ky - N;
-    const int cyx = ny * ny + kx * kx;
     int bin[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int kz = j * M + m;
-      const int nz = kz < N / 2 ? kz : kz - N;
-      const int n2 = nz * nz + cyx;
-      bin[m] = bintab[(ky >= 0 && n2 < NB2) ? n2 : 0];
-    }
+    for (int m = 0; m < M; ++m) bin[m] = nbin[m];
+    __syncthreads();
+    if (e + parts < ntiles) load(tiles[e + parts]);
+    int ky, kx;
+    BT::column(tile, cc, ky, kx);
     fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
     // |nz| is monotone along m, so equal bins come in runs, each added to the
     // thread's own slot once
@@ -1073,6 +1079,7 @@ hipError_t with_storage(int storage, F&& f) {
 #define XS21_PIPE_BLOCKS 2048
 #endif
 constexpr long kPipeBlocks = XS21_PIPE_BLOCKS;
+constexpr long kIonBlocksMax = 16384;   // largest ionisation grid a launch may ask for
 
 unsigned grid_for(long work, long cap) { return static_cast<unsigned>(work < cap ? (work > 0 ? work : 1) : cap); }
 
@@ -1124,9 +1131,10 @@ long bins_live_count(int n) {
 
 // Blocks per spectrum of the binning pass: enough blocks over `outer`
 // spectra to fill the chip, each walking every parts-th live tile.
-long bins_parts(int n, long outer) {
+long bins_parts(int n, long outer, long blocks) {
   const long count = bins_live_count(n);
-  const long k = (kPipeBlocks + outer - 1) / outer;
+  const long target = blocks > 0 ? blocks : kPipeBlocks;
+  const long k = (target + outer - 1) / outer;
   return k < 1 ? 1 : (k > count ? count : k);
 }
 
@@ -1177,7 +1185,15 @@ long bins_tiles(int n) {
 // N = 256) finish in near-even rounds; a grid of only the resident blocks
 // measured slower (row locality of the blocks running together), a finer one
 // no faster and with more x_HI partial sums to reduce.
-int ion_grid(int n) { return static_cast<int>(grid_for(static_cast<long>(n) * n / 2, 8192)); }
+// Default grid of the ionisation pass (the CPU emulation used by the tests
+// builds with a tiny value so that every block walks many row pairs).
+#ifndef XS21_ION_BLOCKS
+#define XS21_ION_BLOCKS 8192
+#endif
+int ion_grid(int n, int blocks) {
+  return static_cast<int>(grid_for(static_cast<long>(n) * n / 2, blocks > 0 ? blocks : XS21_ION_BLOCKS));
+}
+int ion_grid_max(int n) { return static_cast<int>(grid_for(static_cast<long>(n) * n / 2, kIonBlocksMax)); }
 
 int max_group() { return kMaxGroup; }
 int max_radii() { return kNrMax; }
@@ -1212,7 +1228,7 @@ hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, void* ny
 
 hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* out, long nrows, double scale,
                            const long* cut, int batch, long istride, long ostride, const void* tw, int ntab,
-                           hipStream_t s) {
+                           hipStream_t s, int blocks) {
   if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
@@ -1222,7 +1238,8 @@ hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* 
         constexpr int N = decltype(nc)::value;
         const long npairs = nrows / 2;
         const long items = (npairs + RowShape<N>::WB - 1) / RowShape<N>::WB * batch;
-        hipLaunchKernelGGL((k_rows_c2r<T, ST, N>), dim3(grid_for(items, kPipeBlocks)), dim3(RowShape<N>::NT), 0, s,
+        hipLaunchKernelGGL((k_rows_c2r<T, ST, N>), dim3(grid_for(items, blocks > 0 ? blocks : kPipeBlocks)),
+                           dim3(RowShape<N>::NT), 0, s,
                            static_cast<const cplx<T>*>(in), static_cast<ST*>(out), npairs, items,
                            static_cast<T>(scale), cut, istride, ostride, static_cast<const cplx<T>*>(tw), ntab / N);
         return hipGetLastError();
@@ -1285,7 +1302,7 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
 }
 
 hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long inner, long ilim, bool nyquist,
-                                const void* tw, int ntab, hipStream_t s) {
+                                const void* tw, int ntab, hipStream_t s, int blocks) {
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
@@ -1294,13 +1311,14 @@ hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long i
       if (ilim < 1 || ilim > inner || ilim % A::TI != 0 || outer < 1)   // not whole tiles: the plain pass
         return launch_axis(dtype, n, -1, 0, data, data, outer, inner, ilim, nullptr, 1, 0, 0, tw, ntab, s);
       const long ntiles = ilim / A::TI * outer;
+      const unsigned grid = grid_for(ntiles, blocks > 0 ? blocks : kPipeBlocks);
       auto* dp = static_cast<cplx<T>*>(data);
       if (nyquist)
-        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 2>), dim3(grid_for(ntiles, kPipeBlocks)), dim3(A::NT), 0, s, dp, dp,
-                           inner, ilim / A::TI, ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
+        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 2>), dim3(grid), dim3(A::NT), 0, s, dp, dp, inner, ilim / A::TI,
+                           ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
       else
-        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 1>), dim3(grid_for(ntiles, kPipeBlocks)), dim3(A::NT), 0, s, dp, dp,
-                           inner, ilim / A::TI, ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
+        hipLaunchKernelGGL((k_axis_pipe<T, N, -1, 1>), dim3(grid), dim3(A::NT), 0, s, dp, dp, inner, ilim / A::TI,
+                           ntiles, static_cast<const cplx<T>*>(tw), ntab / N);
       return hipGetLastError();
     });
   });
@@ -1405,11 +1423,12 @@ size_t slot_table_bytes() {
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
                       const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
                       double* xpart, const void* tw, int ntab, hipStream_t s, int field_walker, void* x_hi,
-                      void* dtb, void* slot_tab) {
-  if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup) return hipErrorInvalidValue;
+                      void* dtb, void* slot_tab, int blocks, int flag_test) {
+  if (nr < 1 || nr > kNrMax || nw < 1 || nw > kMaxGroup || blocks > kIonBlocksMax) return hipErrorInvalidValue;
   const bool fields = field_walker >= 0;
   if (fields && (field_walker >= nw || !x_hi || !dtb)) return hipErrorInvalidValue;
-  const bool sorted = slot_tab && !zt && dtype == kF32 && ion_sorted_default();
+  const bool want_sorted = flag_test < 0 ? ion_sorted_default() : flag_test == 1;
+  const bool sorted = slot_tab && !zt && dtype == kF32 && want_sorted;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_storage<T>(storage, [&](auto sv) {
@@ -1423,7 +1442,7 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
           constexpr bool SRT = decltype(srt)::value && !decltype(two)::value && std::is_same<T, float>::value;
           const size_t dyn = SRT ? static_cast<size_t>(kNrMax) * kSortWidth * sizeof(T) : 0;
           hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value, decltype(withf)::value, SRT>),
-                             dim3(ion_grid(N)), dim3(IonShape<N>::NT), dyn, s, static_cast<const ST*>(dR),
+                             dim3(ion_grid(N, blocks)), dim3(IonShape<N>::NT), dyn, s, static_cast<const ST*>(dR),
                              static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc),
                              static_cast<const T*>(thr), static_cast<const T*>(zt), nw, static_cast<T>(tb),
                              static_cast<T>(dc), static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,

@@ -17,8 +17,11 @@ constexpr int kBF16 = 2;
 int axis_tile(int n);                   // inner columns per block of the strided passes
 long axis_tiles(int n, long inner);     // blocks along the inner dimension
 long bins_tiles(int n);                 // column tiles per spectrum of the binning z pass
-long bins_parts(int n, long outer);     // partial sums per spectrum written by the binning pass (<= live tiles)
-int ion_grid(int n);                    // blocks of the ionisation pass
+// partial sums per spectrum written by the binning pass (<= live tiles) for a
+// launch of about `blocks` blocks over `outer` spectra (blocks <= 0: default)
+long bins_parts(int n, long outer, long blocks = 0);
+int ion_grid(int n, int blocks = 0);    // blocks of the ionisation pass (blocks <= 0: default)
+int ion_grid_max(int n);                // the largest grid ion_grid may return
 int max_group();                        // walkers per ionisation launch
 int max_radii();                        // radii per ladder
 int thr_stride();                       // padded thresholds per walker (+inf beyond use)
@@ -36,7 +39,7 @@ hipError_t launch_rows_r2c(int dtype, int n, const void* in, void* out, void* ny
 // without being read.
 hipError_t launch_rows_c2r(int dtype, int storage, int n, const void* in, void* out, long nrows, double scale,
                            const long* cut, int batch, long istride, long ostride, const void* tw, int ntab,
-                           hipStream_t s);
+                           hipStream_t s, int blocks = 0);
 // Transform along the middle axis of [outer][n][inner] for columns < ilim
 // (dir -1 forward, +1 inverse), for `batch` slices: slice b reads src + b *
 // sstride and writes dst + b * dstride (elements).  mode 0 plain; mode 1 the
@@ -84,7 +87,7 @@ long bins_live_count(int n);
 // ny^2 + kx^2 > (n/2)^2 are not stored (kx = the column index, or n/2 for
 // every column when nyquist, the Nyquist plane [ky][z]).
 hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long inner, long ilim, bool nyquist,
-                                const void* tw, int ntab, hipStream_t s);
+                                const void* tw, int ntab, hipStream_t s, int blocks = 0);
 // Ionisation + dT_b + forward x pass for nw walkers on one box: spectra
 // [nw][n][n][half_pitch(n)] with kx < n/2, Nyquist planes nyq[nw][y][z].
 // zt == nullptr: constant efficiency, thr[w][max_radii()]; else the
@@ -95,11 +98,16 @@ hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long i
 // launch (field_walker < 0: no fields, x_hi / dtb ignored).
 // slot_tab: device scratch of slot_table_bytes() for the sorted flag test of
 // FP32 constant-efficiency walkers (nullptr: one compare per walker and radius).
+// blocks: grid of the pass (<= 0: ion_grid's default; at most ion_grid_max);
+// flag_test: 1 sorted tables, 0 one compare per walker and radius, -1 default
+// (sorted unless XS21_ION_FLAGS=ballot).  The x_HI partial sums xpart hold
+// one value per walker and block of the grid used.
 size_t slot_table_bytes();
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
                       const void* thr, const void* zt, int nw, double tb, double dc, void* spec, void* nyq,
                       double* xpart, const void* tw, int ntab, hipStream_t s, int field_walker = -1,
-                      void* x_hi = nullptr, void* dtb = nullptr, void* slot_tab = nullptr);
+                      void* x_hi = nullptr, void* dtb = nullptr, void* slot_tab = nullptr, int blocks = 0,
+                      int flag_test = -1);
 // Two-population planning (Section 4, eq. 9) of nw walkers on one box:
 // slots[nr] (device, slot 0 = cell radius), wp[nw] (device) -> thresholds
 // thr[w][2][stride] (lo, hi; +inf where unused), wc[w].upper set where some

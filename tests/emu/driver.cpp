@@ -22,6 +22,8 @@
 //        -> mcmc<tag>_x.bin [steps+1][nw][dim], _lp.bin [steps+1][nw], _acc.bin [steps][nw] int32
 //   batch_fields <nbmax> <walker> <box> -> batchf_{pk,xhi,fx,fd}.bin (fields of that walker on that box)
 //   erfc <file> <count>        -> erfc.bin: the FP32 erfc of the ionisation pass at count floats
+//   tuning <n> <ion> <pipe> <bins> <flag> <group>  -> xs21_set_tuning for grid size n
+//   autotune <reps> <cache> <tag> -> tune<tag>.bin: int32 [ion, pipe, bins, flag, group, from_cache]
 //   smoothed <box> <index>     -> sm_b{b}_j{j}.bin
 //   pk <box> <field file>      -> fpk_b{b}.bin
 #include <cstdio>
@@ -138,6 +140,25 @@ int main(int argc, char** argv) {
       write_file(out + "/batchf_xhi.bin", xm.data(), xm.size() * 8);
       write_file(out + "/batchf_fx.bin", fx.data(), fx.size());
       write_file(out + "/batchf_fd.bin", fd.data(), fd.size());
+    } else if (cmd == "tuning") {
+      int n;
+      xs21_tuning t;
+      is >> n >> t.ion_blocks >> t.pipe_blocks >> t.bins_blocks >> t.flag_test >> t.group;
+      CHECK(xs21_set_tuning(ctx, n, &t));
+    } else if (cmd == "autotune") {
+      int reps;
+      std::string cache, tag;
+      is >> reps >> cache >> tag;
+      const int nb = static_cast<int>(box_n.size());
+      std::vector<xs21_box> bx(nb);
+      for (int i = 0; i < nb; ++i) bx[i] = i;
+      xs21_tuning t;
+      double ms = 0;
+      int cached = -1;
+      CHECK(xs21_autotune(ctx, bx.data(), nb, walkers.data(), static_cast<int>(walkers.size()), reps, cache.c_str(),
+                          &t, &ms, &cached));
+      const int32_t v[6] = {t.ion_blocks, t.pipe_blocks, t.bins_blocks, t.flag_test, t.group, cached};
+      write_file(out + "/tune" + tag + ".bin", v, sizeof v);
     } else if (cmd == "erfc") {
       std::string f;
       long count = 0;

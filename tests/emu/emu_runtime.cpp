@@ -263,3 +263,16 @@ hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
   *p = const_cast<void*>(symbol);
   return hipSuccess;
 }
+
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int device) {
+  if (!p || device != 0) return hipErrorInvalidValue;
+  std::memset(p, 0, sizeof *p);
+  std::strcpy(p->gcnArchName, "emu");
+  return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t*) { return hipErrorNotSupported; }
+hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, char*, size_t) { return hipErrorNotSupported; }
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipErrorNotSupported; }
+hipError_t hipGraphDestroy(hipGraph_t) { return hipErrorNotSupported; }

@@ -45,10 +45,18 @@ enum {
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
   hipErrorInvalidSymbol = 13,
+  hipErrorNotSupported = 801,
   hipErrorNoDevice = 100,
   hipErrorLaunchFailure = 719
 };
 typedef void* hipStream_t;
+typedef struct hipemu_graph* hipGraph_t;
+typedef struct hipemu_graph_exec* hipGraphExec_t;
+typedef enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1,
+               hipStreamCaptureModeRelaxed = 2 } hipStreamCaptureMode;
+struct hipDeviceProp_t {
+  char gcnArchName[256];
+};
 typedef struct hipemu_event* hipEvent_t;
 typedef enum { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
@@ -204,4 +212,13 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipEventDestroy(hipEvent_t e);
 // device address of a __device__ variable: the host object itself here
 hipError_t hipGetSymbolAddress(void** p, const void* symbol);
+// device properties: the architecture name "emu"
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int device);
+// launch graphs are not emulated: every call returns hipErrorNotSupported
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode mode);
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
+hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, void* node, char* log, size_t log_size);
+hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s);
+hipError_t hipGraphExecDestroy(hipGraphExec_t x);
+hipError_t hipGraphDestroy(hipGraph_t g);
 }

@@ -39,10 +39,11 @@ def build() -> str:
     if not _stale():
         return BIN
     os.makedirs(os.path.dirname(BIN), exist_ok=True)
-    # XS21_PIPE_BLOCKS=3: grid-stride kernels run 3 blocks, each over many
-    # items; XS21_BINS_LDS_BUDGET: FP64 binning at N = 16 runs 1 bin per launch
+    # XS21_PIPE_BLOCKS=3 / XS21_ION_BLOCKS=4: grid-stride kernels run 3 or 4
+    # blocks, each over many items; XS21_BINS_LDS_BUDGET: FP64 binning at
+    # N = 16 runs 1 bin per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
-           "-DXS21_PIPE_BLOCKS=3", "-DXS21_BINS_LDS_BUDGET=17664",
+           "-DXS21_PIPE_BLOCKS=3", "-DXS21_ION_BLOCKS=4", "-DXS21_BINS_LDS_BUDGET=17664",
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", *SRC[:NHIP], "-x", "none", *SRC[NHIP:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)

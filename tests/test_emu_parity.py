@@ -399,3 +399,46 @@ def test_emu_erfc_f32():
     bound = 1.2e-7 + (2.0 * z * z + 8.0) * 2.0 ** -24
     worst = int(np.argmax(rel / bound))
     assert np.all(rel <= bound), f"x = {xs[worst]}: relative error {rel[worst]:.3e} > {bound[worst]:.3e}"
+
+
+def test_emu_launch_shapes_and_autotune_cache(tmp_path):
+    """Explicit launch shapes (per-walker flag test, small ionisation grid, walker
+    groups of 3, other pass grids) give the default shapes' results up to the
+    order of FP64 sums; the autotuner writes its choice to a JSON cache under the
+    device / size / dtype / ladder / group key and a second context reads it back
+    without timing (the emulation's event timer reads 0 ms, so the defaults win)."""
+    import json
+    specs = [(16, 32.0, 9.0, 5)]
+    walkers = [(30.0, 15.0, 5e4), (12.0, 8.0, 2e5), (80.0, 19.0, 1.2e4), (45.0, 6.0, 3e4), (0.7, 10.0, 2e4)]
+    cache = str(tmp_path / "tune.json")
+    run = eh.EmuRun(storage="f32", max_walkers=8, phys={"pk_amp": AMP})
+    d = synth.make_box(16, 32.0, 9.0, seed=80, amp=AMP, dtype=np.float32)
+    run.box(d, 32.0, 9.0, 5)
+    for w in walkers:
+        run.walker(*w)
+    run.cmd("prepare")
+    run.cmd("batch 5 a")
+    run.cmd("tuning 16 2 1 1 0 3")
+    run.cmd("batch 5 b")
+    run.cmd(f"autotune 1 {cache} 1")
+    run.run()
+    pa = run.read("batcha_pk.bin", np.float64)
+    pb = run.read("batchb_pk.bin", np.float64)
+    np.testing.assert_allclose(pb, pa, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(run.read("batchb_xhi.bin", np.float64), run.read("batcha_xhi.bin", np.float64),
+                               rtol=1e-12)
+    t1 = run.read("tune1.bin", np.int32)
+    assert t1[5] == 0 and t1[3] == 1 and t1[4] == 8   # timed; sorted flag test; groups up to max_walkers
+    entries = json.load(open(cache))
+    (key, val), = entries.items()
+    assert key == "emu|n=16|f32|f32|nr=%d|g=5" % len(oracle.shared_radii(16, 32.0, PHYS))
+    assert [val[k] for k in ("ion_blocks", "pipe_blocks", "bins_blocks", "flag_test", "group")] == list(t1[:5])
+    run2 = eh.EmuRun(storage="f32", max_walkers=8, phys={"pk_amp": AMP})
+    run2.box(d, 32.0, 9.0, 5)
+    for w in walkers:
+        run2.walker(*w)
+    run2.cmd("prepare")
+    run2.cmd(f"autotune 1 {cache} 2")
+    run2.run()
+    t2 = run2.read("tune2.bin", np.int32)
+    assert t2[5] == 1 and list(t2[:5]) == list(t1[:5])

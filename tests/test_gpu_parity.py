@@ -868,3 +868,97 @@ def test_two_population_bf16_storage_with_velocity(xs):
         assert flips <= 3e-2 and rel <= 5e-2
         assert abs(xhi[i, 0] - ev.xhi_mean) <= 1e-2
     ctx.close()
+
+
+# ------------------------------------------------------------------ launch shapes and graphs
+
+def test_launch_shapes_and_autotune(xs, tmp_path):
+    """Launch shapes change nothing but the order of FP64 sums (the two flag tests
+    are exact): explicit shapes and the autotuner's choice reproduce the default
+    P(k) and mean x_HI; the choice is cached under its key and read back by a
+    second context without timing."""
+    n, box, z, nb = 64, 128.0, 9.0, 12
+    d = synth.make_box(n, box, z, seed=48, amp=AMP, dtype=np.float32)
+    walkers = synth.draw_walkers(40, 17)
+    cache = str(tmp_path / "tuning.json")
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f32", max_walkers=40, max_plain_radii=30)
+    pk0, x0 = (t.cpu().numpy() for t in ctx.eval_batch([b], walkers))
+    res = ctx.autotune([b], walkers, reps=2, cache_path=cache)
+    print(f"[autotune 64^3] {res}", flush=True)
+    assert not res["from_cache"] and res["best_ms"] > 0
+    pk1, x1 = (t.cpu().numpy() for t in ctx.eval_batch([b], walkers))
+    np.testing.assert_allclose(pk1, pk0, rtol=1e-12)
+    np.testing.assert_allclose(x1, x0, rtol=1e-12)
+    ctx.set_tuning(n, ion_blocks=500, pipe_blocks=300, bins_blocks=700, flag_test=0, group=7)
+    pk2, x2 = (t.cpu().numpy() for t in ctx.eval_batch([b], walkers))
+    np.testing.assert_allclose(pk2, pk0, rtol=1e-12)
+    np.testing.assert_allclose(x2, x0, rtol=1e-12)
+    ctx.close()
+    ctx2 = _ctx(xs)
+    b2 = ctx2.add_box(d, box, z, nb)
+    ctx2.prepare("f32", max_walkers=40, max_plain_radii=30)
+    res2 = ctx2.autotune([b2], walkers, reps=2, cache_path=cache)
+    assert res2["from_cache"] and res2["tuning"] == res["tuning"]
+    assert ctx2.get_tuning(n) == res["tuning"]
+    ctx2.close()
+
+
+@pytest.mark.parametrize("dim", [3, 5])
+def test_graph_replay_of_sampler_steps(xs, dim):
+    """An ensemble step recorded into a launch graph on a created stream, launched
+    three times with new uniforms copied in by eager work between the launches,
+    against the same steps called directly: every launch gives the same walkers
+    and ln p bit for bit; calls that synchronise are refused while capturing."""
+    import torch
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):   # torch's work ordered with the context's
+        _graph_case(xs, dim, st)
+    torch.cuda.synchronize()
+
+
+def _graph_case(xs, dim, st):
+    import torch
+    n, box, z, nb = 32, 64.0, 9.0, 6
+    d = synth.make_box(n, box, z, seed=49, amp=AMP, dtype=np.float32)
+    lo, hi = PRIOR3 if dim == 3 else PRIOR5
+    nw, steps = 8, 3
+    x0 = np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * synth.uniforms((nw, dim), 500 + dim)
+    us = synth.uniforms((steps, 2, nw // 2, 3), 510 + dim)
+    ctx = xs.Context(0, stream=st, phys=xs.physics(pk_amp=AMP))
+    h = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f32", max_walkers=4, max_plain_radii=30)
+    fid = (30.0, 15.0, 5e4) if dim == 3 else (70.0, 15.0, 10 ** 4.7, 4 / 3, -1 / 3)
+    fpk, _ = (ctx.eval_batch if dim == 3 else ctx.eval_batch2)([h], [fid])
+    km, _ = ctx.bins(h)
+    ctx.set_mock(h, km ** 3 * fpk.cpu().numpy()[0, 0, :nb] / (2 * np.pi ** 2))
+    spec = xs.sampler(lo, hi)
+    xe = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    xg = xe.clone()
+    lpe = torch.empty(nw, dtype=torch.float64, device="cuda")
+    lpg = torch.empty(nw, dtype=torch.float64, device="cuda")
+    ub = torch.zeros((2, nw // 2, 3), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    pk_pre = torch.empty((1, 1, nb), dtype=torch.float64, device="cuda")
+    xh_pre = torch.empty((1, 1), dtype=torch.float64, device="cuda")
+    ctx.mcmc_lnprob([h], spec, xe, lpe)
+    ctx.mcmc_lnprob([h], spec, xg, lpg)
+    st.synchronize()
+    ctx.capture_begin()
+    with pytest.raises(xs.Xs21Error, match="graph capture"):   # host-planned walkers: refused, nothing recorded
+        (ctx.eval_batch if dim == 3 else ctx.eval_batch2)([h], [fid], pk_pre, xh_pre)
+    ctx.mcmc_step([h], spec, xg, lpg, ub, acc)
+    g = ctx.capture_end()
+    moved = 0
+    for t in range(steps):
+        ut = torch.tensor(us[t], dtype=torch.float64, device="cuda")
+        ub.copy_(ut)
+        ctx.mcmc_step([h], spec, xe, lpe, ut, acc)   # eager reference with the same uniforms
+        g.launch()
+        st.synchronize()
+        moved += int(acc.sum())
+        assert torch.equal(xg, xe) and torch.equal(lpg, lpe), f"launch {t} differs from the direct step"
+    print(f"[graph dim={dim}] {steps} launches equal to direct steps; accepted {moved}", flush=True)
+    g.close()
+    ctx.close()
