@@ -373,11 +373,15 @@ void fill_walker_table(const xs21::plan::WalkerPlan& wp, bool plain, unsigned ch
                        double zeta) {
   const int nr = static_cast<int>(wp.thr.size());
   const int used = plain ? nr : nr - wp.first;
-  WalkerConst<T> c;
+  WalkerConst<T> c{};
   c.zeta = static_cast<T>(zeta);
   c.a_cell = static_cast<T>(wp.a_cell);
   c.chunks = (used + 7) / 8;
-  c.partial = wp.partial ? 1 : 0;
+  // mode 2 iff zeta > 1 (erfc^-1(1/zeta) > 0: the cell-radius threshold
+  // delta_c - sqrt(2 dsig2) erfc^-1(1/zeta) lies below delta_c)
+  c.partial = wp.partial ? (wp.u_star > 0.0 ? 2 : 1) : 0;
+  c.ha = static_cast<float>(0.5 * wp.a_cell);
+  c.a2l = static_cast<float>(wp.a_cell * wp.a_cell * 1.4426950408889634074);
   c.upper = 0;
   std::memcpy(wc_dst, &c, sizeof c);
   const T inf = std::numeric_limits<T>::infinity();
@@ -411,7 +415,7 @@ int first_radius(const BoxRec& b, double r_mfp) {
 
 template <typename T>
 void put_const(unsigned char* dst, double a_cell, int used, bool partial) {
-  WalkerConst<T> c;
+  WalkerConst<T> c{};
   c.zeta = T(1);   // the efficiency lives in the planned thresholds and table
   c.a_cell = static_cast<T>(a_cell);
   c.chunks = (used + 7) / 8;

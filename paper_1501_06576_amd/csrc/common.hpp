@@ -84,28 +84,31 @@ template <>
 __device__ __forceinline__ void store_as_stream<bf16, float>(bf16* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
 
 // Per-(walker, box) constants consumed by the per-cell ionisation pass
-// (32 bytes, 32-byte aligned).
+// (32 bytes for FP32, 64 for FP64; 32-byte aligned).
 template <typename T>
 struct alignas(32) WalkerConst {
   T zeta;      // ionising efficiency
   T a_cell;    // 1 / sqrt(2 (sigma^2(M_min) - sigma^2(R_cell))), valid if partial != 0
   int32_t chunks;   // radius slots tested, in groups of 8 (slots run from the cell radius up)
-  int32_t partial;  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged
+  // 0: no halo above M_min fits in a cell, x_HI = 1 when unflagged;
+  // 1: x_HI = 1 - zeta erfc(a_cell (delta_c - delta_cell)) when unflagged;
+  // 2: the same, and zeta > 1, so that the cell-radius threshold lies below
+  //    delta_c and every unflagged cell has delta_c - delta_cell > 0
+  int32_t partial;
+  float ha;    // a_cell / 2 and a_cell^2 log2(e) in FP32, for the FP32 erfc of a
+  float a2l;   // positive argument (partial == 2)
   int32_t upper;    // two-population walkers: 1 if some slot's flag interval is bounded above
 };
-static_assert(sizeof(WalkerConst<float>) == 32 && sizeof(WalkerConst<double>) == 32, "32-byte records");
+static_assert(sizeof(WalkerConst<float>) == 32 && sizeof(WalkerConst<double>) == 64, "32- and 64-byte records");
 
-// One walker's constants: the fields of the flag test and the partial
-// ionisation (zeta, a_cell, chunks, partial) with one 16-byte load for FP32,
-// so that they arrive together with the radius count; `upper` apart.
+// One walker's constants; for FP32 the whole record in one 32-byte load.
 template <typename T>
 __host__ __device__ __forceinline__ WalkerConst<T> load_walker(const WalkerConst<T>* p) {
   WalkerConst<T> c;
   if constexpr (sizeof(T) == 4) {
-    typedef int32_t V4 __attribute__((vector_size(16)));
-    const V4 raw = *reinterpret_cast<const V4*>(p);
+    typedef int32_t V8 __attribute__((vector_size(32)));
+    const V8 raw = *reinterpret_cast<const V8*>(p);
     __builtin_memcpy(&c, &raw, sizeof raw);
-    c.upper = p->upper;
   } else {
     c = *p;
   }

@@ -113,6 +113,15 @@ __device__ __forceinline__ void unpack_pair(const cplx<T>* z, int k, cplx<T>& A,
   A = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
   B = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
 }
+// The same without the halving, 2A and 2B: for rows stored at half scale
+// (exact: halving commutes with every rounding of the transform).
+template <int N, typename T>
+__device__ __forceinline__ void unpack_pair2(const cplx<T>* z, int k, cplx<T>& A, cplx<T>& B) {
+  const cplx<T> zk = z[k];
+  const cplx<T> zm = z[(N - k) & (N - 1)];
+  A = {zk.x + zm.x, zk.y - zm.y};
+  B = {zk.y + zm.y, zm.x - zk.x};
+}
 
 // ---------------------------------------------------------------------------
 // Forward rows: real [rows][N] -> half spectra [rows][N/2+1]
@@ -648,9 +657,21 @@ __device__ __forceinline__ unsigned long long flag_mask(const T (&d)[NR], int ch
   return m;
 }
 
+// 1 - zeta erfc(a u), u = delta_c - delta_cell, for an unflagged cell of a
+// walker with partial != 0.  FP32 walkers with partial == 2 have u > 0 here
+// (the cell-radius threshold lies below delta_c), which takes the erfc of a
+// positive argument with the cell's u and u^2 formed once for all walkers.
+template <typename T>
+__device__ __forceinline__ T partial_xhi(const WalkerConst<T>& c, T u, T u2) {
+  if constexpr (sizeof(T) == 4) {
+    if (c.partial == 2) return T(1) - c.zeta * erfc_pos(c.ha, c.a2l, u, u2);
+  }
+  return T(1) - c.zeta * erfc_t(c.a_cell * u);
+}
+
 template <typename T, int NR, bool TWO>
 __device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c, const T* thr_w, const T* zt_w,
-                                      T dc) {
+                                      T dc, T u2) {
   // two-population walkers whose intervals are all open above test one end
   unsigned long long m;
   if constexpr (TWO)
@@ -667,7 +688,7 @@ __device__ __forceinline__ T cell_xhi(const T (&d)[NR], const WalkerConst<T>& c,
       const T t = max(c.a_cell * (dc - d[0]), T(0));
       x = T(1) - zeta_eff(zt_w, t) * erfc_t(t);
     } else {
-      x = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
+      x = partial_xhi(c, dc - d[0], u2);
     }
   }
   return x;
@@ -737,65 +758,119 @@ __global__ __launch_bounds__(kSortWidth) void k_slot_tables(const T* __restrict_
   if (w == kSortWidth - 1) P[s * kMaskPitch + kSortWidth] = m | (1ull << id[w]);
 }
 
+// An empty asm taking v in a vector register and giving it back: the value
+// is then opaque to the compiler's algebra and computed in every lane.
+template <typename V>
+__device__ __forceinline__ void in_vgpr(V& v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(v));
+#else
+  (void)v;
+#endif
+}
+
+// One step of the search: 2 H + (e <= d ? s1 : s0), as compare, select and
+// shift-add (three instructions; as plain code the compiler splits the
+// select's group offset into a fourth).  s0 and s1 come in vector registers
+// (the select's VCC read is its one scalar operand).  The device pass writes them out;
+// the host pass (and the CPU build of the tests) evaluates the same formula.
+__device__ __forceinline__ int heap_step(int H, float e, float d, int s0, int s1) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  int t;
+  asm("v_cmp_le_f32_e32 vcc, %[e], %[d]\n\t"
+      "v_cndmask_b32_e32 %[t], %[s0], %[s1], vcc\n\t"
+      "v_lshl_add_u32 %[h], %[h], 1, %[t]"
+      : [h] "+v"(H), [t] "=&v"(t)
+      : [e] "v"(e), [d] "v"(d), [s0] "v"(s0), [s1] "v"(s1)
+      : "vcc");
+  return H;
+#else
+  return 2 * H + (e <= d ? s1 : s0);
+#endif
+}
+__device__ __forceinline__ int heap_step(int H, double e, double d, int s0, int s1) {
+  return 2 * H + (e <= d ? s1 : s0);
+}
+
 // Walker mask of one cell from the sorted tables: E (in LDS) and P (global),
-// for every one of the kNrMax slots.  The cell's delta_R are loaded four
-// slots at a time, one group ahead; slots past the ladder hold only +inf
-// thresholds and re-read the cell radius's value (a cache hit) instead of
-// branching, since a branch would force the pending loads to complete early.
-// The four searches of a group run level by level, so their LDS reads issue
-// together, and the mask reads of a group are consumed only after the next
-// group's searches.  Returns bits 0..31 in lo and 32..63 in hi.
+// for the slot groups that hold the ladder's nr slots.  The cell's delta_R are
+// loaded four slots at a time, one group ahead; slots past the ladder hold
+// only +inf thresholds and re-read the cell radius's value (a cache hit)
+// instead of branching, since a branch would force the pending loads to
+// complete early.  The four searches of a group run level by level, so their
+// LDS reads issue together, and the mask reads of a group are consumed only
+// after the next group's searches.  Loads address a slot's plane (or mask
+// row) from scalars plus one 32-bit offset per lane.  Returns bits 0..31 in
+// lo and 32..63 in hi.
 template <typename T, typename S>
 __device__ __forceinline__ void sorted_flags(const S* __restrict__ dR, size_t n3, size_t cell, int nr, const T* E,
                                              const uint64_t* __restrict__ P, uint32_t& lo, uint32_t& hi) {
-  constexpr int GS = 4, NG = kNrMax / GS;
+  constexpr int GS = 4;
+  constexpr int SZ = static_cast<int>(sizeof(T));
+  constexpr int TREE = kSortWidth * SZ;   // bytes of one slot's tree
   static_assert(kNrMax % GS == 0, "slots come in groups of 4");
-  const auto ld = [&](int s) {
-    return load_as<T>(dR, static_cast<size_t>(nr - 1 - (s < nr ? s : 0)) * n3 + cell);
+  // slots past the ladder have only +inf thresholds (prefix mask 0): the
+  // groups that hold none of the ladder's slots are skipped
+  const int ng = (nr + GS - 1) / GS;
+  // byte offset of the cell in a plane: below 2^32 (N^3 sizeof(S) <= 2^30)
+  const uint32_t cb = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
+  const auto ld = [&](int sl) {
+    const unsigned char* plane =
+        reinterpret_cast<const unsigned char*>(dR + static_cast<size_t>(nr - 1 - (sl < nr ? sl : 0)) * n3);
+    return load_as<T>(reinterpret_cast<const S*>(plane + cb), 0);
   };
   T dn[GS];
 #pragma unroll
   for (int j = 0; j < GS; ++j) dn[j] = ld(j);
   uint64_t acc = 0, pend[GS] = {0, 0, 0, 0};
+  const unsigned char* eb = reinterpret_cast<const unsigned char*>(E);
   // a rolled loop: unrolled, the compiler keeps every slot's base address live
   // across the cell loop (and spills them)
 #pragma unroll 1
-  for (int g = 0; g < NG; ++g) {
+  for (int g = 0; g < ng; ++g) {
     T dv[GS];
 #pragma unroll
     for (int j = 0; j < GS; ++j) dv[j] = dn[j];
-    const int gn = g + 1 < NG ? g + 1 : g;   // the last group re-reads itself (cache hits)
+    const int gn = g + 1 < ng ? g + 1 : g;   // the last group re-reads itself (cache hits)
 #pragma unroll
     for (int j = 0; j < GS; ++j) dn[j] = ld(gn * GS + j);
-    // the search walks byte offsets a = sizeof(T) i of node i within the
-    // slot's tree: child 2i + 1 + b is at 2a + sizeof(T) (1 + b)
-    const unsigned char* eb = reinterpret_cast<const unsigned char*>(E + g * GS * kSortWidth);
-    int a[GS];
+    // Node h of a slot's tree (heap order from 1: children 2h and 2h + 1)
+    // sits at byte H = G + SZ (h - 1) from the group's first tree, G = the
+    // group's byte offset in E.  A step to child 2h + b is H' = 2H - G +
+    // SZ (1 + b): one select between two group constants and one shift-add,
+    // and the address needs no further add (E's place in LDS and the slot's
+    // tree offset fold into the read's constant offset).
+    const int G = g * GS * TREE;
+    int step0 = SZ - G, step1 = 2 * SZ - G;
+    in_vgpr(step0);   // in registers: the select reads VCC, its one scalar operand
+    in_vgpr(step1);
+    int H[GS];
 #pragma unroll
-    for (int j = 0; j < GS; ++j) a[j] = 0;
+    for (int j = 0; j < GS; ++j) {
+      H[j] = G;
+      in_vgpr(H[j]);
+    }
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
       T e[GS];
 #pragma unroll
-      for (int j = 0; j < GS; ++j) e[j] = *reinterpret_cast<const T*>(eb + j * kSortWidth * sizeof(T) + a[j]);
+      for (int j = 0; j < GS; ++j) e[j] = *reinterpret_cast<const T*>(eb + j * TREE + H[j]);
 #pragma unroll
-      for (int j = 0; j < GS; ++j)
-        a[j] = 2 * a[j] + (e[j] <= dv[j] ? static_cast<int>(2 * sizeof(T)) : static_cast<int>(sizeof(T)));
+      for (int j = 0; j < GS; ++j) H[j] = heap_step(H[j], e[j], dv[j], step0, step1);
     }
     uint64_t cur[GS];
 #pragma unroll
     for (int j = 0; j < GS; ++j) {
-      // a = sizeof(T) (63 + k), k in [0, 63]; S_63 sits at E[63], read at
-      // offset (a - 63 sizeof(T)) | 63 sizeof(T) = (k | 63) sizeof(T), which
-      // is 63 sizeof(T) for every k in [0, 63] (sizeof(T) a power of two), so
-      // that the read stays with the search: a constant LDS address would be
-      // hoisted out of the cell loop into a register per slot
-      const T last = *reinterpret_cast<const T*>(eb + j * kSortWidth * sizeof(T) +
-                                                 ((a[j] - 63 * static_cast<int>(sizeof(T))) |
-                                                  (63 * static_cast<int>(sizeof(T)))));
-      int k = a[j] / static_cast<int>(sizeof(T)) - (kSortWidth - 1);
+      // h = 64 + k, k in [0, 63], so H - G = SZ (63 + k) < GS TREE and G is a
+      // multiple of GS TREE: S_63 (E[63] of the slot) is read at
+      // (H & -(GS TREE)) + 63 SZ, an address computed from the search so that
+      // the read stays with it (a constant LDS address would be hoisted out
+      // of the cell loop into a register per slot)
+      const T last = *reinterpret_cast<const T*>(eb + j * TREE + (H[j] & -(GS * TREE)) + 63 * SZ);
+      int k = static_cast<int>(static_cast<uint32_t>(H[j] - G) / SZ) - (kSortWidth - 1);
       k += static_cast<int>(k == kSortWidth - 1) & static_cast<int>(last <= dv[j]);
-      cur[j] = P[(g * GS + j) * kMaskPitch + k];
+      const unsigned char* row = reinterpret_cast<const unsigned char*>(P + (g * GS + j) * kMaskPitch);
+      cur[j] = *reinterpret_cast<const uint64_t*>(row + static_cast<uint32_t>(k) * 8u);
     }
 #pragma unroll
     for (int j = 0; j < GS; ++j) {
@@ -882,13 +957,14 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   const int lane = t & 63;
   const int row = t / N, x = t % N;
   T* ldsr = reinterpret_cast<T*>(lds);
-  // SORTED: the search trees of the group's slots, E[nr][64] (dynamic LDS)
-  HIP_DYNAMIC_SHARED(unsigned char, ion_dyn)
-  T* El = reinterpret_cast<T*>(ion_dyn);
+  // SORTED: the search trees of the group's slots, E[nr][64], at a fixed LDS
+  // address (so that the search's reads fold it into their offsets)
+  __shared__ T El[SORTED ? kNrMax * kSortWidth : 1];
   if constexpr (SORTED)
-    for (int e = t; e < kNrMax * kSortWidth; e += IS::NT) El[e] = Eg[e];
+    for (int e = t; e < (nr + 3) / 4 * 4 * kSortWidth; e += IS::NT) El[e] = Eg[e];
   for (int w = t; w < kMaxGroup; w += IS::NT) acc[w] = 0.0;
   load_twiddles<N>(twl, tw, tstride);
+  const T tbh = T(0.5) * tb;
   for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
     const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
     // ballot test: every slot's delta_R in registers for the walker loop;
@@ -902,6 +978,8 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
       load_radii<T, S>(dR, N3, cell, nr, d);
     }
     const T od = odens[cell];
+    const T u = dc - d[0];   // argument of the partial ionisation, per cell
+    const T u2 = u * u;
     // Every delta_R of the cell is in its register before the walker loop:
     // otherwise the compiler, unable to see that the loads have landed after
     // the first walker, keeps one load-counter wait per radius inside the loop
@@ -910,33 +988,39 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
     for (int s = 0; s < (SORTED ? 1 : kNrMax); ++s) asm volatile("" ::"v"(d[s]));
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
+      // SORTED: the batch's walkers' bits of the cell's mask, from bit 0 (a
+      // batch lies within one 32-walker half)
+      const uint32_t mb = (w0 < 32 ? mlo : mhi) >> (w0 & 31);
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
         T xh;
         if constexpr (SORTED) {
+          static_assert(32 % IS::WB == 0, "a walker batch must lie within one half of the mask");
           const WalkerConst<T> c = load_walker(wc + w);
-          const uint32_t half = w < 32 ? mlo : mhi;
           xh = T(1);
-          if ((half >> (w & 31)) & 1u)
+          if ((mb >> q) & 1u)
             xh = T(0);
           else if (c.partial)
-            xh = T(1) - c.zeta * erfc_t(c.a_cell * (dc - d[0]));
+            xh = partial_xhi(c, u, u2);
         } else {
           xh = cell_xhi<T, (SORTED ? 1 : kNrMax), TWO>(d, load_walker(wc + w),
                                                        thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
-                                                       zt + static_cast<size_t>(w) * kZetaPitch, dc);
+                                                       zt + static_cast<size_t>(w) * kZetaPitch, dc, u2);
         }
-        const T tv = tb * xh * od;
-        ldsr[2 * (q * N + x) + row] = tv;
+        // dT_b at half scale (tbh = tb / 2): the unpacking after the
+        // transform then needs no halving, with bitwise the same spectrum
+        const T tvh = tbh * xh * od;
+        ldsr[2 * (q * N + x) + row] = tvh;
         if constexpr (FIELDS) {
           if (w == fw) {
             fx[cell] = xh;
-            fd[cell] = tv;
+            fd[cell] = tvh + tvh;   // exactly tb xh od
           }
         }
         if constexpr (IS::NT >= 64) {
-          const T s = row_sum(xh);
+          T s = row_sum(xh);
+          in_vgpr(s);   // the last DPP step in every lane, fused with its add
           if ((lane & 15) == 0) wsum[q][t >> 4] = s;
         } else {
           wsum[q][t] = xh;
@@ -949,23 +1033,33 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
         acc[w0 + t] += s;
       }
       fft_team<N, -1, T, typename IS::Plan>(lds + (t / IS::TS) * N, 1, t % IS::TS, twl, 1);
-      for (int idx = t; idx < IS::WB * IS::H; idx += IS::NT) {
-        const int q = idx / IS::H, k = idx % IS::H;
-        const int w = w0 + q;
-        if (w < nw) {
-          cplx<T> A, B;
-          unpack_pair<N>(lds + q * N, k, A, B);
-          if (k < N / 2) {
-            cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
-            store_stream(o + k, A);
-            store_stream(o + IS::HP + k, B);
-          } else {
-            const size_t z = static_cast<size_t>(2 * p) / N, y = static_cast<size_t>(2 * p) % N;
-            cplx<T>* o = nyq + (static_cast<size_t>(w) * N + y) * N + z;
-            o[0] = A;
-            o[N] = B;
+      // kx < N/2: thread t takes kx = t mod N/2 of the batch's walkers
+      // t / (N/2), + NT / (N/2), ... (a whole wave on one walker for N >= 128)
+      {
+        constexpr int HALF = N / 2;
+        constexpr int QS = IS::NT / HALF;   // walkers per pass (4)
+        static_assert(IS::NT % HALF == 0 && IS::WB % QS == 0, "unpack passes must tile the batch");
+        const int k = t % HALF, q0 = t / HALF;
+        cplx<T>* o = spec + static_cast<size_t>(w0 + q0) * SPEC + static_cast<size_t>(2 * p) * IS::HP + k;
+#pragma unroll
+        for (int i = 0; i < IS::WB / QS; ++i) {
+          const int q = q0 + i * QS;
+          if (w0 + q < nw) {
+            cplx<T> A, B;
+            unpack_pair2<N>(lds + q * N, k, A, B);
+            store_stream(o + static_cast<size_t>(i) * QS * SPEC, A);
+            store_stream(o + static_cast<size_t>(i) * QS * SPEC + IS::HP, B);
           }
         }
+      }
+      // the Nyquist column kx = N/2 of each walker, into its own plane
+      if (t < IS::WB && w0 + t < nw) {
+        cplx<T> A, B;
+        unpack_pair2<N>(lds + t * N, N / 2, A, B);
+        const size_t z = static_cast<size_t>(2 * p) / N, y = static_cast<size_t>(2 * p) % N;
+        cplx<T>* o = nyq + (static_cast<size_t>(w0 + t) * N + y) * N + z;
+        o[0] = A;
+        o[N] = B;
       }
       __syncthreads();
     }
@@ -1440,9 +1534,8 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
                                                   static_cast<size_t>(kNrMax) * kSortWidth * sizeof(double));
         auto go = [&](auto two, auto withf, auto srt) {
           constexpr bool SRT = decltype(srt)::value && !decltype(two)::value && std::is_same<T, float>::value;
-          const size_t dyn = SRT ? static_cast<size_t>(kNrMax) * kSortWidth * sizeof(T) : 0;
           hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value, decltype(withf)::value, SRT>),
-                             dim3(ion_grid(N, blocks)), dim3(IonShape<N>::NT), dyn, s, static_cast<const ST*>(dR),
+                             dim3(ion_grid(N, blocks)), dim3(IonShape<N>::NT), 0, s, static_cast<const ST*>(dR),
                              static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc),
                              static_cast<const T*>(thr), static_cast<const T*>(zt), nw, static_cast<T>(tb),
                              static_cast<T>(dc), static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,

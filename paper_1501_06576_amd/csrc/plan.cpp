@@ -125,6 +125,7 @@ WalkerPlan walker(const xs21_physics& p, double z, const double* radii, int nr, 
   const double inv_zeta = 1.0 / w.zeta;
   const bool can_flag = inv_zeta < 2.0;  // zeta f_coll >= 1 needs f_coll >= 1/zeta, and f_coll < 2
   const double u_star = can_flag ? erfcinv(inv_zeta) : 0.0;
+  out.u_star = u_star;
   const double inf = std::numeric_limits<double>::infinity();
   out.first = nr - 1;
   for (int j = 0; j < nr; ++j) {

@@ -41,6 +41,7 @@ struct WalkerPlan {
   double m_min = 0.0;
   double a_cell = 0.0;        // 1 / sqrt(2 dsig2 at the cell radius)
   bool partial = false;       // dsig2 at the cell radius > 0
+  double u_star = 0.0;        // erfc^-1(1/zeta) (0 when zeta <= 1/2: nothing flags)
 };
 
 // Thresholds of one walker on a radius list (eq. 1 rewritten with erfc^-1).

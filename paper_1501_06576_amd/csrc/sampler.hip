@@ -66,11 +66,15 @@ __global__ __launch_bounds__(64) void k_plan1(const double* __restrict__ par, in
     t[s] = v;
   }
   const double dcell = s_min - slots[0].s_r;
-  WalkerConst<T> c;
+  const double a = dcell > 0.0 ? 1.0 / sqrt(2.0 * dcell) : 0.0;
+  WalkerConst<T> c{};
   c.zeta = static_cast<T>(zeta);
-  c.a_cell = static_cast<T>(dcell > 0.0 ? 1.0 / sqrt(2.0 * dcell) : 0.0);
+  c.a_cell = static_cast<T>(a);
   c.chunks = (used + 7) / 8;
-  c.partial = dcell > 0.0 ? 1 : 0;
+  // mode 2 iff zeta > 1: the cell-radius threshold lies below delta_c
+  c.partial = dcell > 0.0 ? (ustar > 0.0 ? 2 : 1) : 0;
+  c.ha = static_cast<float>(0.5 * a);
+  c.a2l = static_cast<float>(a * a * 1.4426950408889634074);
   c.upper = 0;
   wc[w] = c;
 }
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(64) void k_walker2(const double* __restrict__ par, 
   o.pad = 0;
   wp[w] = o;
   const double ds = slots[0].ds_cool;
-  WalkerConst<T> c;
+  WalkerConst<T> c{};
   c.zeta = T(1);
   c.a_cell = static_cast<T>(ds > 0.0 ? 1.0 / sqrt(2.0 * ds) : 0.0);
   c.chunks = (used + 7) / 8;

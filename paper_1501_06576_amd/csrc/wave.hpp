@@ -96,22 +96,37 @@ __device__ __forceinline__ int wave_max(int v) {
 // erfc(x) = t exp(-z^2 + P(t)), t = 1 / (1 + z/2), z = |x|, P a degree-9
 // Chebyshev fit (Press, Teukolsky, Vetterling & Flannery, Numerical Recipes,
 // 2nd ed., section 6.2, "erfcc"): fractional error below 1.2e-7 for all x;
-// erfc(-z) = 2 - erfc(z).  The reciprocal and exponential are the hardware's
-// approximate ones (about 1 ulp each).
+// erfc(-z) = 2 - erfc(z).  Evaluated as t 2^(P'(t) - z^2 log2 e) with P' =
+// P log2 e (coefficients scaled in double, rounded once), so that for x = a u
+// the walker part (a/2, a^2 log2 e) and the cell part (u, u^2) of the
+// argument are formed once each: erfc_pos below.  The reciprocal and the
+// base-2 exponential are the hardware's approximate ones (about 1 ulp each).
+namespace erfc_detail {
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr float c(double v) { return static_cast<float>(v * kLog2e); }
+}  // namespace erfc_detail
+
+// erfc(a u) for a u >= 0, from ha = a / 2, a2l = a^2 log2(e), u and u2 = u^2.
+__device__ __forceinline__ float erfc_pos(float ha, float a2l, float u, float u2) {
+  using erfc_detail::c;
+  const float t = __builtin_amdgcn_rcpf(fmaf(ha, u, 1.0f));  // v_rcp_f32, 1 ulp
+  float p = c(0.17087277);
+  p = fmaf(p, t, c(-0.82215223));
+  p = fmaf(p, t, c(1.48851587));
+  p = fmaf(p, t, c(-1.13520398));
+  p = fmaf(p, t, c(0.27886807));
+  p = fmaf(p, t, c(-0.18628806));
+  p = fmaf(p, t, c(0.09678418));
+  p = fmaf(p, t, c(0.37409196));
+  p = fmaf(p, t, c(1.00002368));
+  p = fmaf(p, t, c(-1.26551223));
+  return t * __builtin_amdgcn_exp2f(fmaf(-a2l, u2, p));   // v_exp_f32, 1 ulp
+}
+
 __device__ __forceinline__ float erfc_fast(float x) {
+  constexpr float kL = static_cast<float>(erfc_detail::kLog2e);
   const float z = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);  // v_rcp_f32, 1 ulp
-  float p = 0.17087277f;
-  p = fmaf(p, t, -0.82215223f);
-  p = fmaf(p, t, 1.48851587f);
-  p = fmaf(p, t, -1.13520398f);
-  p = fmaf(p, t, 0.27886807f);
-  p = fmaf(p, t, -0.18628806f);
-  p = fmaf(p, t, 0.09678418f);
-  p = fmaf(p, t, 0.37409196f);
-  p = fmaf(p, t, 1.00002368f);
-  p = fmaf(p, t, -1.26551223f);
-  const float r = t * __expf(fmaf(-z, z, p));
+  const float r = erfc_pos(0.5f, kL, z, z * z);
   return x >= 0.0f ? r : 2.0f - r;
 }
 

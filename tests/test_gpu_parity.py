@@ -416,7 +416,8 @@ def test_uneven_bf16_storage(xs, ojobs):
     for (i, bi), (fx, fd) in fields.items():
         res = ojobs[("uneven", i, bi)].result()
         flips, rel, dx, dd = _field_check(f"uneven-bf16 fields w{i} box{bi}", fx, fd, res, pk[i, bi], xhi[i, bi])
-        assert flips <= 2e-3 and rel <= 1e-2
+        # observed at most 4.5e-4 flipped cells and 2.9e-3 P(k) relative error
+        assert flips <= 1.5e-3 and rel <= 1e-2
     print("[uneven-bf16] walker box   n  flips-n/a  pk_rel_max  |dxhi_mean|", flush=True)
     worst_rel, worst_xm = 0.0, 0.0
     for bi, sp in enumerate(wl.boxes):
@@ -430,7 +431,8 @@ def test_uneven_bf16_storage(xs, ojobs):
             worst_rel, worst_xm = max(worst_rel, rel), max(worst_xm, dxm)
     print(f"[uneven-bf16] 4 walkers x 6 boxes: worst P(k) rel {worst_rel:.2e}, worst |dx_HI mean| {worst_xm:.2e}",
           flush=True)
-    assert worst_rel <= 1e-2 and worst_xm <= 2e-3
+    # observed at most 3.5e-3 and 2.5e-4
+    assert worst_rel <= 1e-2 and worst_xm <= 8e-4
 
 
 def test_large_512_box(xs, ojobs):
