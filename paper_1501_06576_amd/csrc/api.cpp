@@ -648,7 +648,7 @@ hipError_t mem_stage(xs21_ctx* c, hipStream_t st, const BoxRec& b, const EvalSlo
   });
   if (e != hipSuccess) return e;
   // the binning pass reads the live tiles (TI columns x N values each)
-  e = timed(c, st, XS21_K_AXIS_BINS, count * ntl * xs21::axis_tile_cols(b.n) * n * 2 * rs, [&] {
+  e = timed(c, st, XS21_K_AXIS_BINS, count * ntl * xs21::bins_tile_cols(b.n) * n * 2 * rs, [&] {
     return xs21::launch_axis_bins(b.dtype, b.n, sl.spec, sl.nyq, count, parts,
                                   reinterpret_cast<const int32_t*>(c->ws + b.off_bins_live),
                                   static_cast<long>(b.bins_live.size()),

@@ -83,6 +83,13 @@ __device__ __forceinline__ void store_as_stream(S* p, size_t i, T v) {
 template <>
 __device__ __forceinline__ void store_as_stream<bf16, float>(bf16* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
 
+// Columns (complex values) per tile of the binning pass's strided reads, and
+// of the HBM probe that mimics them.  (Overridable for timing variants.)
+#ifndef XS21_BINS_TI
+#define XS21_BINS_TI 8
+#endif
+constexpr int kBinsTileCols = XS21_BINS_TI;
+
 // Per-(walker, box) constants consumed by the per-cell ionisation pass
 // (32 bytes for FP32, 64 for FP64; 32-byte aligned).
 template <typename T>

@@ -96,6 +96,21 @@ struct AxisShape {
   static constexpr int NT = TI * TS;
 };
 
+// Threads of the binning pass: the strided passes' FFT teams over at most
+// kBinsTileCols columns per tile (and at most the strided passes' TI), but
+// never fewer than one wave per block (the final reduction runs one wave per
+// bin).  At 256^3, 8 columns (64-byte segments, 256-thread blocks, 5 blocks
+// per CU) measured 4 % faster than 16 (512-thread blocks, 2 per CU).
+template <int N>
+struct BinShape {
+  using Plan = typename AxisShape<N>::Plan;
+  static constexpr int TS = AxisShape<N>::TS;
+  static constexpr int TIA = AxisShape<N>::TI < kBinsTileCols ? AxisShape<N>::TI : kBinsTileCols;
+  static constexpr int TI = TIA * TS >= 64 ? TIA : 64 / TS;
+  static constexpr int NT = TI * TS;
+  static_assert(NT % 64 == 0 && TI <= AxisShape<N>::TI, "binning blocks are whole waves");
+};
+
 __device__ __forceinline__ float erfc_t(float x) { return erfc_fast(x); }
 __device__ __forceinline__ double erfc_t(double x) { return erfc(x); }
 
@@ -441,10 +456,10 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 // Forward z pass fused with |X|^2 binning.  src [outer][N][N * HP] holds the
 // x- and y-transformed spectra (padded rows, kx < N/2) and nyq [outer][N][N]
 // their Nyquist planes kx = N/2 as [ky][z].  Tiles cover live columns only
-// and keep 128-byte aligned loads: "main" tiles are 16 consecutive kx < KM of
-// one y (KM = the largest multiple of 16 <= N/2), "rest" tiles gather the
-// remaining columns (kx in [KM, N/2], the Nyquist plane for N >= 32) of 16
-// consecutive (y, kx) pairs.  Block i of a spectrum's `parts` blocks takes
+// and keep aligned loads: "main" tiles are TI consecutive kx < KM of one y
+// (KM = the largest multiple of TI <= N/2; TI = 8 at N = 256, 64-byte
+// segments), "rest" tiles gather the remaining columns (kx in [KM, N/2], the
+// Nyquist plane for N >= 32) of TI consecutive (y, kx) pairs.  Block i of a spectrum's `parts` blocks takes
 // entries i, i + parts, i + 2 parts, ... of the list `tiles` (so that blocks
 // running together read neighbouring tiles), accumulates its bin sums over
 // them and writes FP64 sums of w |X|^2 for bins [b0, b0 + nbc) to
@@ -487,14 +502,14 @@ struct BinTiles {
 };
 
 template <typename T, int N>
-__global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src,
+__global__ __launch_bounds__(BinShape<N>::NT) void k_axis_bins(const cplx<T>* __restrict__ src,
                                                                 const cplx<T>* __restrict__ nyq, long parts,
                                                                 const int32_t* __restrict__ tiles, long ntiles,
                                                                 const int8_t* __restrict__ bintab,
                                                                 int nbins, int b0, int nbc, BinSlots bs,
                                                                 double* __restrict__ part,
                                                                 const cplx<T>* __restrict__ tw, int tstride) {
-  using A = AxisShape<N>;
+  using A = BinShape<N>;
   using BT = BinTiles<N, A::TI>;
   constexpr int HP = Half<N>::HP;
   constexpr long PLANE = static_cast<long>(N) * HP;  // stride between z planes
@@ -1199,10 +1214,10 @@ std::vector<int32_t> bins_live_tiles(int n) {
   std::vector<int32_t> out;
   (void)with_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    using BT = BinTiles<N, AxisShape<N>::TI>;
+    using BT = BinTiles<N, BinShape<N>::TI>;
     for (long t = 0; t < BT::COUNT; ++t) {
       bool live = false;
-      for (int cc = 0; cc < AxisShape<N>::TI && !live; ++cc) {
+      for (int cc = 0; cc < BinShape<N>::TI && !live; ++cc) {
         int ky, kx;
         BT::column(t, cc, ky, kx);
         const int ny = ky < N / 2 ? ky : ky - N;
@@ -1269,7 +1284,7 @@ long bins_tiles(int n) {
   long count = 0;
   (void)with_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    count = BinTiles<N, AxisShape<N>::TI>::COUNT;
+    count = BinTiles<N, BinShape<N>::TI>::COUNT;
     return hipSuccess;
   });
   return count;
@@ -1418,6 +1433,15 @@ hipError_t launch_axis_fwd_disk(int dtype, int n, void* data, long outer, long i
   });
 }
 
+int bins_tile_cols(int n) {
+  int ti = 0;
+  (void)with_n(n, [&](auto nc) {
+    ti = BinShape<decltype(nc)::value>::TI;
+    return hipSuccess;
+  });
+  return ti;
+}
+
 int axis_tile_cols(int n) {
   int ti = 0;
   (void)with_n(n, [&](auto nc) {
@@ -1472,7 +1496,7 @@ hipError_t launch_axis_bins(int dtype, int n, const void* src, const void* nyq, 
     using T = decltype(tv);
     return with_n(n, [&](auto nc) {
       constexpr int N = decltype(nc)::value;
-      using A = AxisShape<N>;
+      using A = BinShape<N>;
       constexpr long stat = (static_cast<long>(N) * A::TI + N) * static_cast<long>(sizeof(cplx<T>));
       const auto slot_bytes = [](const BinSlots& bs) { return static_cast<long>(bs.rows) * A::TI * 8; };
       hipError_t e = hipSuccess;

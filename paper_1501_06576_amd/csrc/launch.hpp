@@ -55,6 +55,8 @@ hipError_t launch_axis(int dtype, int n, int dir, int mode, const void* src, voi
 // Columns per tile of the strided passes at size n (tile t covers flat
 // columns t * cols .. t * cols + cols - 1 of a padded half spectrum).
 int axis_tile_cols(int n);
+// Columns per tile of the binning pass at size n (its live-tile lists use it).
+int bins_tile_cols(int n);
 // Mode 1 of launch_axis over a list of live tiles only: ntiles entries
 // tiles[k] = (r << 24) | tile, each a tile with at least one column inside
 // the disk |n|^2 <= cut[2 (r - r0)] of radius r of the batch starting at r0;

@@ -70,31 +70,36 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const F4* __restri
   if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(in + i), out + i);
 }
 
-// Strided tiles of [nsp][N][N][HP] complex FP32 spectra (N = 256, HP = 144):
-// a tile is the 128-byte segment kx in [16 c, 16 c + 16) of row (z, y) for
-// all N values of z (every segment of the padded rows, so the whole buffer is
-// read once); the block's 256 threads read 16 z-planes x 16 complex values
-// per step, as the binning pass does, 16 steps per tile.
+// Strided tiles of [nsp][N][N][HP] complex FP32 spectra (N = 256, HP = 144),
+// the binning pass's z-strided reads in whole lines: a tile is the 128-byte
+// segment kx in [16 c, 16 c + 16) of row (z, y) for all N values of z (every
+// segment of the padded rows, so the whole buffer is read once; blocks
+// running together read neighbouring segments); the block's 256 threads read
+// 16 z-planes x 16 complex values per step.  (The pass itself reads 64-byte
+// halves of these lines from neighbouring blocks; as a probe that pattern
+// measured slower than the pass, so the whole-line form is the ceiling.)
 constexpr int kTileN = 256;
 constexpr int kTileHP = 144;
 constexpr int kTileSeg = 16;   // complex values per 128-byte segment
+static_assert(kTileHP % kTileSeg == 0 && kProbeThreads % kTileSeg == 0, "segments tile the rows and the block");
 
 __global__ __launch_bounds__(kProbeThreads) void k_probe_tile(const cplx<float>* __restrict__ in, long ntiles,
                                                               float* __restrict__ sink) {
   constexpr long PLANE = static_cast<long>(kTileN) * kTileHP;
   constexpr long SPEC = PLANE * kTileN;
-  constexpr int SEGS = kTileHP / kTileSeg;        // segments per row (9, the last one padding in the pass)
+  constexpr int SEGS = kTileHP / kTileSeg;        // segments per row
+  constexpr int ZR = kProbeThreads / kTileSeg;    // z-planes per step
   const int c = threadIdx.x % kTileSeg, zr = threadIdx.x / kTileSeg;
   float acc = 0.0f;
   for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const long sp = t / (static_cast<long>(kTileN) * SEGS), r = t % (static_cast<long>(kTileN) * SEGS);
     const long y = r / SEGS, seg = r % SEGS;
     const cplx<float>* base = in + sp * SPEC + y * kTileHP + seg * kTileSeg + c;
-    cplx<float> v[kTileN / 16];
+    cplx<float> v[kTileN / ZR];
 #pragma unroll
-    for (int k = 0; k < kTileN / 16; ++k) v[k] = base[(zr + 16 * k) * PLANE];
+    for (int k = 0; k < kTileN / ZR; ++k) v[k] = base[(zr + ZR * k) * PLANE];
 #pragma unroll
-    for (int k = 0; k < kTileN / 16; ++k) acc += v[k].x + v[k].y;
+    for (int k = 0; k < kTileN / ZR; ++k) acc += v[k].x + v[k].y;
   }
   __shared__ float red[kProbeThreads];
   red[threadIdx.x] = acc;

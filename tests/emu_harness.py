@@ -16,7 +16,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 EMU = os.path.join(HERE, "emu")
-BIN = os.path.join(EMU, "_build", "xs21_emu")
+# XS21_EMU_DEFINES: extra -D flags (space separated) for checking a build
+# variant on the CPU; such builds get a binary of their own
+EXTRA_DEFINES = os.environ.get("XS21_EMU_DEFINES", "").split()
+BIN = os.path.join(EMU, "_build", "xs21_emu" + ("_" + "_".join(d.lstrip("-D").replace("=", "-")
+                                                                for d in EXTRA_DEFINES) if EXTRA_DEFINES else ""))
 SRC = [os.path.join(ROOT, "paper_1501_06576_amd", "csrc", f)
        for f in ("kernels.hip", "likelihood.hip", "two_population.hip", "sampler.hip", "probe.hip", "static_scratch.hip",
                  "api.cpp", "plan.cpp")]
@@ -43,7 +47,7 @@ def build() -> str:
     # blocks, each over many items; XS21_BINS_LDS_BUDGET: FP64 binning at
     # N = 16 runs 1 bin per launch
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
-           "-DXS21_PIPE_BLOCKS=3", "-DXS21_ION_BLOCKS=4", "-DXS21_BINS_LDS_BUDGET=17664",
+           "-DXS21_PIPE_BLOCKS=3", "-DXS21_ION_BLOCKS=4", "-DXS21_BINS_LDS_BUDGET=17664", *EXTRA_DEFINES,
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-x", "c++", *SRC[:NHIP], "-x", "none", *SRC[NHIP:], *EXTRA,
            "-o", BIN + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
