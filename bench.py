@@ -95,6 +95,14 @@ def measured_valu(kernel: str, workload: str):
     return t["kernels"][kernel]["valu_insts_per_launch"]
 
 
+def measured_valu_busy(kernel: str, workload: str):
+    """rocprofv3's VALUBusy (percent) for kernel class `kernel` from the committed run, or None."""
+    t = _profile_json(VALU_FILE, workload)
+    if t is None or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel].get("valu_busy_pct")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -208,7 +216,29 @@ def summarize_profiles(directory: str, bench_json: str, workload: str, commands:
             fh.write("\n".join(lines) + "\n")
         log(f"wrote {TRAFFIC_FILE}")
 
+    util = [c for c in ("VALUBusy", "VALUUtilization", "LdsUtil", "LDSBankConflict") if c in runs]
     sq = [c for c in runs if c.startswith("SQ_")]
+    if util:
+        med = {c: {n: statistics.median(vs) for n, vs in per_kernel(c).items()} for c in util}
+        names = sorted(set().union(*(m.keys() for m in med.values())))
+        with open(os.path.join(prof_dir, f"utilization_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 derived metrics per dispatch, percent (median over dispatches): {workload} workload\n")
+            for c in commands:
+                if "VALUBusy" in c:
+                    fh.write(f"# command: {c}\n")
+            fh.write("# VALUBusy: share of the kernel's time the CUs' vector ALUs issue; VALUUtilization: active\n"
+                     "# lanes per VALU instruction; LdsUtil: share of time LDS is busy; LDSBankConflict: share of\n"
+                     "# time LDS is stalled by bank conflicts\n")
+            fh.write(f"# kernel source hash: {src_hash}\n\n")
+            fh.write(f"{'kernel':52s} " + " ".join(f"{c[:15]:>15s}" for c in util) + "\n")
+            for name in names:
+                if kernel_class(name) in (None, "probe"):
+                    continue
+                fh.write(f"{_short(name):52s} " + " ".join(f"{med[c].get(name, 0.0):15.1f}" for c in util) + "\n")
+        log(f"wrote utilization_{tag}.txt")
+        busy = med.get("VALUBusy", {})
+    else:
+        busy = {}
     if sq:
         med = {c: {n: statistics.median(vs) for n, vs in per_kernel(c).items()} for c in sq}
         names = sorted(set().union(*(m.keys() for m in med.values())))
@@ -224,9 +254,10 @@ def summarize_profiles(directory: str, bench_json: str, workload: str, commands:
                          + f" {waves:9.0f}")
             if cls not in kernels or valu > kernels[cls]["valu_insts_per_launch"]:
                 kernels[cls] = {"valu_insts_per_launch": valu, "waves_per_launch": waves, "kernel": _short(name),
-                                "per_wave": {c: row[c] / waves for c in sq if c != "SQ_WAVES"}}
-        t = {"source_hash": src_hash, "workload": workload, "commands": [c for c in commands if "SQ_" in c],
-             "kernels": kernels}
+                                "per_wave": {c: row[c] / waves for c in sq if c != "SQ_WAVES"},
+                                "valu_busy_pct": busy.get(name)}
+        t = {"source_hash": src_hash, "workload": workload,
+             "commands": [c for c in commands if "SQ_" in c or "VALUBusy" in c], "kernels": kernels}
         with open(VALU_FILE, "w") as fh:
             json.dump(t, fh, indent=1)
         with open(os.path.join(prof_dir, f"sq_counters_{tag}.txt"), "w") as fh:
@@ -294,7 +325,8 @@ def roofline(prof, steps, workload):
     if valu is not None:
         lanes = valu * 64 / (avg_ms * 1e-3) / 1e12
         out["valu"] = {"insts_per_launch": valu, "achieved": round(lanes, 3), "peak": round(VALU_PEAK_TLANES, 2),
-                       "unit": "T lane-instructions/s", "frac": round(lanes / VALU_PEAK_TLANES, 4)}
+                       "unit": "T lane-instructions/s", "frac": round(lanes / VALU_PEAK_TLANES, 4),
+                       "valu_busy_pct_counter": measured_valu_busy(dom, workload)}
     else:
         out["valu"] = None
     return out
@@ -473,15 +505,21 @@ def section_plain_configs(xs, torch, amp, reps):
     return out
 
 
-def section_workload(xs, torch, amp, name, reps, group=64, graph=False):
-    """Full step and steady state of another workload, with its kernel table and roofline."""
+def section_workload(xs, torch, amp, name, reps, group=64, graph=False, oracle_box=False):
+    """Full step and steady state of another workload, with its kernel table and roofline;
+    oracle_box: the FP64 oracle timed on one walker x the first box beside the GPU's
+    steady-state time per walker-box."""
     wl = synth.WORKLOADS[name]
     walkers = synth.workload_walkers(wl)
     b = Batch(xs, torch, wl, amp, walkers, group=group)
     tuning = b.autotune()
     ms_step = b.timed(b.step, reps)
-    b.ctx.profile(True)
     ms_steady = b.timed(b.steady, reps)
+    # kernel table: exactly `reps` further steady-state batches under the
+    # library's event timing (after the warm-up above)
+    b.ctx.profile(True)
+    for _ in range(reps):
+        b.steady()
     prof = b.ctx.profile_read()
     b.ctx.profile(False)
     cellr = cell_radii(b.ctx, b.hs, wl.boxes, walkers)
@@ -494,6 +532,19 @@ def section_workload(xs, torch, amp, name, reps, group=64, graph=False):
            "tuning": tuning}
     if graph:
         out["steady_state"]["graph"] = b.graph_steady(reps)
+    if oracle_box:
+        import oracle
+        log(f"timing the FP64 CPU oracle on one walker x one box of {name}")
+        w, s0 = walkers[0], wl.boxes[0]
+        radii = oracle.walker_radii(b.ctx.radii(b.hs[0]), w[1])
+        t0 = time.perf_counter()
+        oracle.evaluate(b.boxes[0], s0.box_mpc, s0.z, w, radii, s0.n_bins, oracle.Physics(pk_amp=amp))
+        dt = time.perf_counter() - t0
+        gpu_s = ms_steady * 1e-3 / (b.nw * len(b.hs))
+        out["cpu_baseline_walker_box"] = {
+            "oracle_s": round(dt, 3), "cores": oracle.FFT_WORKERS, "kind": "oracle",
+            "sample": f"walker {tuple(w)} on box 0 ({s0.n}^3 / {s0.box_mpc:g} Mpc, z = {s0.z:g}, {len(radii)} radii)",
+            "gpu_steady_s_per_walker_box": round(gpu_s, 7), "gpu_over_oracle": round(dt / gpu_s, 1)}
     b.close()
     return out
 
@@ -772,7 +823,7 @@ def main():
         log("uneven BF16 workload (128^3 / 256^3 x 3 z, 256 walkers)")
         result["uneven_mix"] = section_workload(xs, torch, amp, "uneven-mix", max(2, args.steps // 3), graph=True)
         log("large workload (512^3 x 3 z, 1024 walkers)")
-        result["large_512"] = section_workload(xs, torch, amp, "large-512", 1, graph=True)
+        result["large_512"] = section_workload(xs, torch, amp, "large-512", 1, graph=True, oracle_box=True)
 
     props = torch.cuda.get_device_properties(0)
     result["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),

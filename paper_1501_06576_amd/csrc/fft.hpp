@@ -118,12 +118,30 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T>* __restrict__ tw, int m
   return w;
 }
 
+// Synchronisation between the reads and writes of a stage: the whole block,
+// or (WAVE) only the compiler's ordering within the wave.  WAVE holds when
+// every team lies within one wave and only its team touches a sequence: the
+// lanes of a wave issue each LDS instruction together and LDS executes one
+// wave's instructions in order, so a lane reads what another lane of its wave
+// wrote before, and the wave's reads of a stage precede its writes.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage of radix R after spans of length NS are complete.
 // Butterflies b = j, j + TS, ... (N/R of them); results overwrite buf in place,
 // so the stage reads everything into registers, synchronises, then writes.
-template <int N, int R, int NS, int DIR, typename T, int TS>
+template <int N, int R, int NS, int DIR, typename T, int TS, bool WAVE = false>
 __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, const cplx<T>* __restrict__ tw,
                                                int tstride) {
+  static_assert(!WAVE || (TS <= 64 && 64 % TS == 0), "wave-level stages need teams within one wave");
   constexpr int NB = N / R;          // butterflies in this stage
   constexpr int BPT = NB / TS;       // butterflies per thread
   static_assert(NB % TS == 0, "team size must divide the butterfly count");
@@ -140,7 +158,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, cons
     }
     Dft<R, DIR, T>::run(v[q]);
   }
-  __syncthreads();
+  stage_sync<WAVE>();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int b = j + q * TS;
@@ -148,20 +166,22 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, cons
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[(o + r * NS) * es] = v[q][r];
   }
-  __syncthreads();
+  stage_sync<WAVE>();
 }
 
 // Full length-N transform of the sequence buf[0], buf[es], ..., buf[(N-1) es]
 // by team member j in [0, TS).  Every thread of the block must call this
 // (it synchronises the block); data must be in LDS and visible on entry.
 // DIR = -1: X[k] = sum_n x[n] exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
-template <int N, int DIR, typename T, typename Plan = FftPlan<N>>
+// WAVE: the team lies within one wave and synchronises only there (the
+// caller synchronises the block before and after, as its data needs).
+template <int N, int DIR, typename T, typename Plan = FftPlan<N>, bool WAVE = false>
 __device__ __forceinline__ void fft_team(cplx<T>* buf, int es, int j, const cplx<T>* __restrict__ tw,
                                          int tstride) {
   using P = FftShape<N, Plan>;
-  stockham_stage<N, P::R0, 1, DIR, T, P::TS>(buf, es, j, tw, tstride);
-  if constexpr (P::R1 > 1) stockham_stage<N, P::R1, P::R0, DIR, T, P::TS>(buf, es, j, tw, tstride);
-  if constexpr (P::R2 > 1) stockham_stage<N, P::R2, P::R0 * P::R1, DIR, T, P::TS>(buf, es, j, tw, tstride);
+  stockham_stage<N, P::R0, 1, DIR, T, P::TS, WAVE>(buf, es, j, tw, tstride);
+  if constexpr (P::R1 > 1) stockham_stage<N, P::R1, P::R0, DIR, T, P::TS, WAVE>(buf, es, j, tw, tstride);
+  if constexpr (P::R2 > 1) stockham_stage<N, P::R2, P::R0 * P::R1, DIR, T, P::TS, WAVE>(buf, es, j, tw, tstride);
 }
 
 // Copies the twiddles of a length-N transform into LDS (twl[m] = exp(-2 pi i m / N)).

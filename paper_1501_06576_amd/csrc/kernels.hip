@@ -108,6 +108,13 @@ struct BinShape {
   static constexpr int TIA = AxisShape<N>::TI < kBinsTileCols ? AxisShape<N>::TI : kBinsTileCols;
   static constexpr int TI = TIA * TS >= 64 ? TIA : 64 / TS;
   static constexpr int NT = TI * TS;
+  // Tiles per 16-column group: with 8-column tiles, the two halves of each
+  // 128-byte line of FP32 modes.  A block takes its tiles a group at a time
+  // (the second half's load issues while the first is transformed), so both
+  // halves of a line are read by one CU, through one XCD's L2: consecutive
+  // blocks run on different XCDs, and a line read half by each of two would
+  // be fetched from HBM twice.
+  static constexpr int G = TI < 16 ? 16 / TI : 1;
   static_assert(NT % 64 == 0 && TI <= AxisShape<N>::TI, "binning blocks are whole waves");
 };
 
@@ -162,7 +169,8 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restric
       lds[q * N + t] = v;
     }
     __syncthreads();
-    fft_team<N, -1, T, typename S::Plan>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    fft_team<N, -1, T, typename S::Plan, true>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    __syncthreads();   // the row teams synchronised only within their waves
     for (int idx = t; idx < S::WB * S::H; idx += S::NT) {
       const int q = idx / S::H, k = idx % S::H;
       const long p = p0 + q;
@@ -244,7 +252,8 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
     __syncthreads();
     const long r = g / groups, p0 = (g % groups) * S::WB;
     if (g + gridDim.x < nitems) load(g + gridDim.x);
-    fft_team<N, +1, T, typename S::Plan>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    fft_team<N, +1, T, typename S::Plan, true>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
+    __syncthreads();   // the row teams synchronised only within their waves
     ST* dst = out + r * ostride;
 #pragma unroll
     for (int q = 0; q < S::WB; ++q) {
@@ -459,13 +468,15 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 // and keep aligned loads: "main" tiles are TI consecutive kx < KM of one y
 // (KM = the largest multiple of TI <= N/2; TI = 8 at N = 256, 64-byte
 // segments), "rest" tiles gather the remaining columns (kx in [KM, N/2], the
-// Nyquist plane for N >= 32) of TI consecutive (y, kx) pairs.  Block i of a spectrum's `parts` blocks takes
-// entries i, i + parts, i + 2 parts, ... of the list `tiles` (so that blocks
-// running together read neighbouring tiles), accumulates its bin sums over
-// them and writes FP64 sums of w |X|^2 for bins [b0, b0 + nbc) to
-// part[spectrum][i][nbins].  The list holds the tiles with at least one column
-// ny^2 + kx^2 <= (N/2)^2: no mode of the other columns is ever binned (the
-// y pass does not even store them).
+// Nyquist plane for N >= 32) of TI consecutive (y, kx) pairs.  Block i of a
+// spectrum's `parts` blocks takes the groups i, i + parts, i + 2 parts, ... of
+// G consecutive entries of the list `tiles` (BinShape::G; blocks running
+// together read neighbouring groups), accumulates its bin sums over them
+// and writes FP64 sums of w |X|^2 for bins [b0, b0 + nbc) to
+// part[spectrum][i][nbins].  The list holds the groups with at least one
+// column ny^2 + kx^2 <= (N/2)^2: no mode of the other columns is ever binned
+// (the y pass does not even store them; whatever such a column holds stays in
+// its own z transform and meets only the bin entry of the dropped DC mode).
 // Weights w: 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere (half spectrum).
 //
 // Every sum is FP64: |X|^2 of a mode is formed in T, each thread adds its
@@ -568,9 +579,13 @@ __global__ __launch_bounds__(BinShape<N>::NT) void k_axis_bins(const cplx<T>* __
       nbin[m] = bintab[(live && n2 < NB2) ? n2 : 0];
     }
   };
+  // list entry of this block's i-th tile: groups first, first + parts, ...
+  // of A::G consecutive entries (increasing in i)
+  const auto entry = [&](long i) { return (first + (i / A::G) * parts) * A::G + (i % A::G); };
   __syncthreads();  // slots cleared before any thread adds to them
-  if (first < ntiles) load(tiles[first]);
-  for (long e = first; e < ntiles; e += parts) {
+  long e = entry(0);
+  if (e < ntiles) load(tiles[e]);
+  for (long i = 0; e < ntiles; ++i) {
     const long tile = tiles[e];
 #pragma unroll
     for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
@@ -578,7 +593,8 @@ __global__ __launch_bounds__(BinShape<N>::NT) void k_axis_bins(const cplx<T>* __
 #pragma unroll
     for (int m = 0; m < M; ++m) bin[m] = nbin[m];
     __syncthreads();
-    if (e + parts < ntiles) load(tiles[e + parts]);
+    const long en = entry(i + 1);
+    if (en < ntiles) load(tiles[en]);
     int ky, kx;
     BT::column(tile, cc, ky, kx);
     fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
@@ -601,6 +617,7 @@ __global__ __launch_bounds__(BinShape<N>::NT) void k_axis_bins(const cplx<T>* __
     }
     if (cur >= 0) slot[(brow + cur) * A::TI + cc] += run;
     __syncthreads();  // the FFT buffer is read before the next tile is stored
+    e = en;
   }
   // one wave per bin adds the slots of that bin over every (team index,
   // column) in a fixed order (deterministic)
@@ -1047,7 +1064,10 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
         for (int k = 0; k < NPS; ++k) s += static_cast<double>(wsum[t][k]);
         acc[w0 + t] += s;
       }
-      fft_team<N, -1, T, typename IS::Plan>(lds + (t / IS::TS) * N, 1, t % IS::TS, twl, 1);
+      // each row's team lies within one wave: its stages synchronise only
+      // there, the block before (above) and after
+      fft_team<N, -1, T, typename IS::Plan, true>(lds + (t / IS::TS) * N, 1, t % IS::TS, twl, 1);
+      __syncthreads();
       // kx < N/2: thread t takes kx = t mod N/2 of the batch's walkers
       // t / (N/2), + NT / (N/2), ... (a whole wave on one walker for N >= 128)
       {
@@ -1215,15 +1235,19 @@ std::vector<int32_t> bins_live_tiles(int n) {
   (void)with_n(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     using BT = BinTiles<N, BinShape<N>::TI>;
-    for (long t = 0; t < BT::COUNT; ++t) {
+    constexpr int G = BinShape<N>::G;
+    // whole groups of G tiles (the halves of one line stay together)
+    for (long t0 = 0; t0 < BT::COUNT; t0 += G) {
       bool live = false;
-      for (int cc = 0; cc < BinShape<N>::TI && !live; ++cc) {
-        int ky, kx;
-        BT::column(t, cc, ky, kx);
-        const int ny = ky < N / 2 ? ky : ky - N;
-        live = ky >= 0 && ny * ny + kx * kx <= (N / 2) * (N / 2);
-      }
-      if (live) out.push_back(static_cast<int32_t>(t));
+      for (long t = t0; t < t0 + G && t < BT::COUNT && !live; ++t)
+        for (int cc = 0; cc < BinShape<N>::TI && !live; ++cc) {
+          int ky, kx;
+          BT::column(t, cc, ky, kx);
+          const int ny = ky < N / 2 ? ky : ky - N;
+          live = ky >= 0 && ny * ny + kx * kx <= (N / 2) * (N / 2);
+        }
+      if (live)
+        for (long t = t0; t < t0 + G && t < BT::COUNT; ++t) out.push_back(static_cast<int32_t>(t));
     }
     return hipSuccess;
   });

@@ -39,6 +39,8 @@ hipError_t last_error(hipError_t set) {
 
 void syncthreads() { g_block_bar->arrive_and_wait(); }
 
+void wave_sync() { tl_wave->bar->arrive_and_wait(); }
+
 int lane_id() { return tl_lane; }
 
 void wave_exchange(const void* in, void* out, size_t bytes, int src_lane) {

@@ -75,6 +75,7 @@ extern thread_local idx3 tl_thread;
 extern thread_local idx3 tl_block;
 extern dim3 g_grid, g_block;
 void syncthreads();
+void wave_sync();
 void wave_exchange(const void* in, void* out, size_t bytes, int src_lane);
 int lane_id();
 unsigned long long wave_ballot(bool pred);
@@ -93,6 +94,10 @@ hipError_t last_error(hipError_t set = -1);
 #define blockDim (::hipemu::g_block)
 
 inline void __syncthreads() { ::hipemu::syncthreads(); }
+// a wave's lanes run as threads here: the wave-level ordering point is a
+// barrier over the wave's threads
+inline void __builtin_amdgcn_wave_barrier() { ::hipemu::wave_sync(); }
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
 
 template <typename T>
 inline T __shfl_xor(T v, int mask, int width = 64) {
