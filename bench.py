@@ -543,7 +543,8 @@ def section_workload(xs, torch, amp, name, reps, group=64, graph=False, oracle_b
         gpu_s = ms_steady * 1e-3 / (b.nw * len(b.hs))
         out["cpu_baseline_walker_box"] = {
             "oracle_s": round(dt, 3), "cores": oracle.FFT_WORKERS, "kind": "oracle",
-            "sample": f"walker {tuple(w)} on box 0 ({s0.n}^3 / {s0.box_mpc:g} Mpc, z = {s0.z:g}, {len(radii)} radii)",
+            "sample": f"walker ({float(w[0]):.4g}, {float(w[1]):.4g} Mpc, {float(w[2]):.4g} K) on box 0 "
+                      f"({s0.n}^3 / {s0.box_mpc:g} Mpc, z = {s0.z:g}, {len(radii)} radii)",
             "gpu_steady_s_per_walker_box": round(gpu_s, 7), "gpu_over_oracle": round(dt / gpu_s, 1)}
     b.close()
     return out
