@@ -156,7 +156,7 @@ def _counter_runs(directory):
     return out
 
 
-def summarize_profiles(directory: str, bench_json: str, workload: str, commands: list):
+def summarize_profiles(directory: str, bench_json: str, workload: str, commands: list, tag: str = None):
     """Writes profiles/traffic.json, profiles/valu.json and their text tables from the
     rocprofv3 counter runs under `directory` (FETCH_SIZE and WRITE_SIZE runs of
     `bench.py --calibrate`, an SQ counter run), and profiles/kernels_<workload>.txt from
@@ -164,11 +164,12 @@ def summarize_profiles(directory: str, bench_json: str, workload: str, commands:
     taken (the fiducial mock's single-walker launches are a minority)."""
     import glob
     import statistics
-    with open(bench_json) as fh:
-        bench = json.loads(fh.read().strip().splitlines()[-1])
-    cal = bench["calibration"]
     runs = _counter_runs(directory)
-    tag = workload.replace("-", "")
+    cal = None
+    if bench_json:
+        with open(bench_json) as fh:
+            cal = json.loads(fh.read().strip().splitlines()[-1]).get("calibration")
+    tag = tag or workload.replace("-", "")
     src_hash = kernel_source_hash()
     prof_dir = os.path.join(ROOT, "profiles")
 
@@ -179,7 +180,7 @@ def summarize_profiles(directory: str, bench_json: str, workload: str, commands:
         return by
 
     fetch, write = per_kernel("FETCH_SIZE"), per_kernel("WRITE_SIZE")
-    if fetch and write:
+    if fetch and write and cal:
         def probe(d, kind):
             vals = [v for n, vs in d.items() if f"k_probe_{kind}" in n for v in vs]
             return statistics.median(vals) * 1024.0 if vals else None
@@ -575,13 +576,14 @@ def main():
                     help="no GPU work: write the profiles/ summaries from the rocprofv3 output under DIR")
     ap.add_argument("--bench-json", help="with --summarize: the JSON line of the profiled --calibrate run")
     ap.add_argument("--commands", help="with --summarize: file holding the profiling commands, one a line")
+    ap.add_argument("--tag", help="with --summarize: name part of the text summaries (default: the workload)")
     args = ap.parse_args()
     if args.summarize:
         cmds = []
         if args.commands:
             with open(args.commands) as fh:
                 cmds = [c.strip() for c in fh if c.strip()]
-        summarize_profiles(args.summarize, args.bench_json, args.workload, cmds)
+        summarize_profiles(args.summarize, args.bench_json, args.workload, cmds, args.tag)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by walkers and "
