@@ -169,6 +169,30 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int es, int j, cons
   stage_sync<WAVE>();
 }
 
+// The first stage from registers, in two calls.  fft_first_from_regs: the
+// caller already holds its butterfly's inputs v[r] = x[j + r N/R0] (team
+// member j; one butterfly per member, i.e. TS = N / R0); the stage transforms
+// them and writes the outputs to buf (the caller has synchronised the block
+// if buf may still be in use).  fft_rest: synchronises the block and runs
+// the remaining stages.  Between the two the caller may reuse v's registers
+// (say, for the next loads).
+template <int N, int DIR, typename T, typename Plan = FftPlan<N>>
+__device__ __forceinline__ void fft_first_from_regs(cplx<T> (&v)[Plan::R0], cplx<T>* buf, int es, int j) {
+  using P = FftShape<N, Plan>;
+  static_assert(N / P::R0 == P::TS, "one first-stage butterfly per team member");
+  Dft<P::R0, DIR, T>::run(v);
+  // autosorted output of butterfly b = j with spans of 1: positions j R0 + r
+#pragma unroll
+  for (int r = 0; r < P::R0; ++r) buf[(j * P::R0 + r) * es] = v[r];
+}
+template <int N, int DIR, typename T, typename Plan = FftPlan<N>, bool WAVE = false>
+__device__ __forceinline__ void fft_rest(cplx<T>* buf, int es, int j, const cplx<T>* __restrict__ tw, int tstride) {
+  using P = FftShape<N, Plan>;
+  stage_sync<WAVE>();
+  if constexpr (P::R1 > 1) stockham_stage<N, P::R1, P::R0, DIR, T, P::TS, WAVE>(buf, es, j, tw, tstride);
+  if constexpr (P::R2 > 1) stockham_stage<N, P::R2, P::R0 * P::R1, DIR, T, P::TS, WAVE>(buf, es, j, tw, tstride);
+}
+
 // Full length-N transform of the sequence buf[0], buf[es], ..., buf[(N-1) es]
 // by team member j in [0, TS).  Every thread of the block must call this
 // (it synchronises the block); data must be in LDS and visible on entry.

@@ -428,10 +428,11 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 #pragma unroll
     for (int k = 0; k < L; ++k) pre[k] = load_stream(src + off + static_cast<long>(k) * NSTEP * inner);
   }
+  static_assert(L == FftShape<N, typename A::Plan>::R0, "a thread's loads are its first-stage butterfly");
   for (; g < ntiles; g += gridDim.x) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
-    __syncthreads();
+    // the loaded rows n0 + k NSTEP are this thread's first-stage butterfly:
+    // that stage runs in registers, which then take the next tile's loads
+    fft_first_from_regs<N, DIR, T, typename A::Plan>(pre, lds + c, A::TI, n0);
     const long off = offset(g);
     const long gn = g + gridDim.x;
     if (gn < ntiles) {
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 #pragma unroll
       for (int k = 0; k < L; ++k) pre[k] = load_stream(src + offn + static_cast<long>(k) * NSTEP * inner);
     }
-    fft_team<N, DIR, T, typename A::Plan>(lds + c, A::TI, n0, twl, 1);
+    fft_rest<N, DIR, T, typename A::Plan>(lds + c, A::TI, n0, twl, 1);
     int kx2 = 0;
     if constexpr (DISK == 1) {
       const int kx = static_cast<int>((g % tiles_x) * A::TI) + c;
@@ -585,19 +586,21 @@ __global__ __launch_bounds__(BinShape<N>::NT) void k_axis_bins(const cplx<T>* __
   __syncthreads();  // slots cleared before any thread adds to them
   long e = entry(0);
   if (e < ntiles) load(tiles[e]);
+  static_assert(L == FftShape<N, typename A::Plan>::R0, "a thread's loads are its first-stage butterfly");
   for (long i = 0; e < ntiles; ++i) {
     const long tile = tiles[e];
-#pragma unroll
-    for (int k = 0; k < L; ++k) lds[t + k * A::NT] = pre[k];
+    // the loaded rows j + k NSTEP are this thread's first-stage butterfly:
+    // that stage runs on them in registers (no LDS round trip), then the
+    // registers take the next tile's loads
     int bin[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) bin[m] = nbin[m];
-    __syncthreads();
+    fft_first_from_regs<N, -1, T, typename A::Plan>(pre, lds + cc, A::TI, j);
     const long en = entry(i + 1);
     if (en < ntiles) load(tiles[en]);
     int ky, kx;
     BT::column(tile, cc, ky, kx);
-    fft_team<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
+    fft_rest<N, -1, T, typename A::Plan>(lds + cc, A::TI, j, twl, 1);
     // |nz| is monotone along m, so equal bins come in runs, each added to the
     // thread's own slot once
     const T w = (kx == 0 || kx == N / 2) ? T(1) : T(2);
@@ -1102,6 +1105,155 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   for (int w = t; w < nw; w += IS::NT) xpart[static_cast<size_t>(w) * gridDim.x + blockIdx.x] = acc[w];
 }
 
+// Sum over the TS lanes of each aligned team (TS a power of two <= 64), in
+// every lane of the team, in a fixed order.
+template <int TS, typename T>
+__device__ __forceinline__ T team_sum(T v) {
+  if constexpr (TS >= 16) {
+    v = row_sum(v);
+    if constexpr (TS >= 32) v += __shfl_xor(v, 16);
+    if constexpr (TS >= 64) v += __shfl_xor(v, 32);
+  } else {
+#pragma unroll
+    for (int o = TS / 2; o >= 1; o /= 2) v += __shfl_xor(v, o);
+  }
+  return v;
+}
+
+// Ionisation + dT_b + forward x pass for a group of constant-efficiency FP32
+// walkers with the sorted flag test, organised around the x-pass FFT teams.
+// Per row pair (rows 2p, 2p+1; one cell per thread) the block first finds
+// each cell's walker mask (sorted_flags) and keeps it with u = delta_c -
+// delta_cell and (1 + delta) in LDS.  Then for each batch of WB walkers, team
+// q (TS consecutive threads, within one wave) takes walker w0 + q: member j
+// forms the packed row's elements j + r TS (r < R0) — the cells x = j + r TS
+// of both rows — which are exactly its first-stage butterfly, so that stage
+// runs in registers; the remaining stages, the unpacking into the half
+// spectra and the stores are the team's own (wave-level synchronisation
+// only), and so is the walker's x_HI sum: per thread a pairwise FP32 sum of
+// its 2 R0 cells (relative error at most 4 units of FP32 rounding for these
+// non-negative terms), then the team's sum in double.  Block barriers: two
+// per row pair.  Results equal k_ion_rows' (same per-cell arithmetic and
+// transform; the x_HI sums in another order).
+template <typename S, int N, bool FIELDS>
+__global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) void k_ion_teams(
+    const S* __restrict__ dR, const float* __restrict__ odens, int nr, const WalkerConst<float>* __restrict__ wc,
+    int nw, float tb, float dc, cplx<float>* __restrict__ spec, cplx<float>* __restrict__ nyq,
+    double* __restrict__ xpart, const cplx<float>* __restrict__ tw, int tstride, int fw, float* __restrict__ fx,
+    float* __restrict__ fd, const float* __restrict__ Eg, const uint64_t* __restrict__ Pg) {
+  using T = float;
+  using IS = IonShape<N>;
+  using P = FftShape<N, typename IS::Plan>;
+  constexpr int TS = IS::TS, WB = IS::WB, R0 = P::R0, NT = IS::NT;
+  static_assert(N / R0 == TS && WB * TS == NT && 32 % WB == 0, "teams of the x pass");
+  static_assert((N / 2) % TS == 0, "the unpacking splits evenly over a team");
+  constexpr size_t N3 = static_cast<size_t>(N) * N * N;
+  constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
+  __shared__ cplx<T> lds[WB * N];
+  __shared__ cplx<T> twl[N];
+  __shared__ T El[kNrMax * kSortWidth];
+  // per cell of the row pair: walker mask halves (walkers 0..31, 32..63),
+  // u = delta_c - delta_cell and (1 + delta) times the velocity factor
+  __shared__ uint32_t cmask[2][NT];
+  __shared__ T cu[NT], cod[NT];
+  __shared__ double acc[kMaxGroup];
+  const int t = threadIdx.x;
+  const int row = t / N, x = t % N;   // the cell of the mask phase
+  const int q = t / TS, j = t % TS;   // the team and member of the walker phase
+  for (int e = t; e < (nr + 3) / 4 * 4 * kSortWidth; e += NT) El[e] = Eg[e];
+  for (int w = t; w < kMaxGroup; w += NT) acc[w] = 0.0;
+  load_twiddles<N>(twl, tw, tstride);
+  const T tbh = T(0.5) * tb;   // dT_b at half scale: the unpacking needs no halving
+  cplx<T>* my = lds + q * N;   // the team's packed row
+  for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
+    {
+      const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
+      uint32_t mlo = 0, mhi = 0;
+      sorted_flags<T, S>(dR, N3, cell, nr, El, Pg, mlo, mhi);
+      const T d0 = load_as<T>(dR, static_cast<size_t>(nr - 1) * N3 + cell);
+      cmask[0][t] = mlo;
+      cmask[1][t] = mhi;
+      cu[t] = dc - d0;
+      cod[t] = odens[cell];
+    }
+    __syncthreads();
+    for (int w0 = 0; w0 < nw; w0 += WB) {
+      // teams past the group's end repeat its last walker and store nothing
+      // (every lane keeps to the wave-level synchronisation)
+      const int w = min(w0 + q, nw - 1);
+      const bool live = w0 + q < nw;
+      const WalkerConst<T> c = load_walker(wc + w);
+      const uint32_t* cm = cmask[w0 < 32 ? 0 : 1];   // a batch lies within one half
+      const uint32_t bit = 1u << (w & 31);
+      cplx<T> v[R0];
+      T xs[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int xx = j + r * TS;
+        T xh2[2], tv2[2];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const int e = rr * N + xx;
+          const T u = cu[e];
+          T xh = T(1);
+          if (cm[e] & bit)
+            xh = T(0);
+          else if (c.partial)
+            xh = partial_xhi(c, u, u * u);
+          xh2[rr] = xh;
+          tv2[rr] = tbh * xh * cod[e];
+          if constexpr (FIELDS) {
+            if (live && w == fw) {
+              const size_t cell = static_cast<size_t>(2 * p + rr) * N + xx;
+              fx[cell] = xh;
+              fd[cell] = tv2[rr] + tv2[rr];   // exactly tb xh od
+            }
+          }
+        }
+        // dT_b rounded before the transform, as k_ion_rows stores it (no
+        // multiply-add contraction into the first butterfly): the spectra
+        // of the two kernels are bitwise equal
+        in_vgpr(tv2[0]);
+        in_vgpr(tv2[1]);
+        v[r] = {tv2[0], tv2[1]};
+        xs[r] = xh2[0] + xh2[1];
+      }
+      // the walker's x_HI partial sum: pairwise over the thread's values, then the team
+#pragma unroll
+      for (int h = R0 / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int r = 0; r < h; ++r) xs[r] += xs[r + h];
+      const double tot = team_sum<TS>(static_cast<double>(xs[0]));
+      if (live && j == 0) acc[w] += tot;
+      // the packed row's transform, the team alone
+      fft_first_from_regs<N, -1, T, typename IS::Plan>(v, my, 1, j);
+      fft_rest<N, -1, T, typename IS::Plan, true>(my, 1, j, twl, 1);
+      if (live) {
+        cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
+#pragma unroll
+        for (int i = 0; i < (N / 2) / TS; ++i) {
+          const int k = j + i * TS;
+          cplx<T> A, B;
+          unpack_pair2<N>(my, k, A, B);
+          store_stream(o + k, A);
+          store_stream(o + IS::HP + k, B);
+        }
+        if (j == 0) {   // the Nyquist column kx = N/2, into its own plane
+          cplx<T> A, B;
+          unpack_pair2<N>(my, N / 2, A, B);
+          const size_t z = static_cast<size_t>(2 * p) / N, y = static_cast<size_t>(2 * p) % N;
+          cplx<T>* on = nyq + (static_cast<size_t>(w) * N + y) * N + z;
+          on[0] = A;
+          on[N] = B;
+        }
+      }
+      stage_sync<true>();   // the team's row is read before the next batch writes it
+    }
+    __syncthreads();   // the cell values are read before the next row pair writes them
+  }
+  for (int w = t; w < nw; w += NT) xpart[static_cast<size_t>(w) * gridDim.x + blockIdx.x] = acc[w];
+}
+
 // Per-cell density factor of dT_b (Section 2.2, eq. 4): odens = (1 + delta) /
 // (1 + t), t = dv_r/dr / H = -g limited to [-tmax, tmax], with g the
 // line-of-sight gradient field (g == nullptr: odens = 1 + delta).
@@ -1598,6 +1750,19 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
                              static_cast<const T*>(thr), nw, E, P);
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
+          if constexpr (std::is_same<T, float>::value) {
+            const auto teams = [&](auto withf) {
+              hipLaunchKernelGGL((k_ion_teams<ST, N, decltype(withf)::value>), dim3(ion_grid(N, blocks)),
+                                 dim3(IonShape<N>::NT), 0, s, static_cast<const ST*>(dR),
+                                 static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc), nw,
+                                 static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec),
+                                 static_cast<cplx<T>*>(nyq), xpart, static_cast<const cplx<T>*>(tw), ntab / N,
+                                 field_walker, static_cast<T*>(x_hi), static_cast<T*>(dtb),
+                                 static_cast<const T*>(E), static_cast<const uint64_t*>(P));
+              return hipGetLastError();
+            };
+            return fields ? teams(std::true_type{}) : teams(std::false_type{});
+          }
           return fields ? go(std::false_type{}, std::true_type{}, std::true_type{})
                         : go(std::false_type{}, std::false_type{}, std::true_type{});
         }

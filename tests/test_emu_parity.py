@@ -403,8 +403,11 @@ def test_emu_erfc_f32():
 
 def test_emu_launch_shapes_and_autotune_cache(tmp_path):
     """Explicit launch shapes (per-walker flag test, small ionisation grid, walker
-    groups of 3, other pass grids) give the default shapes' results up to the
-    order of FP64 sums; the autotuner writes its choice to a JSON cache under the
+    groups of 3, other pass grids) give the default shapes' results: P(k) up to
+    the order of FP64 sums, mean x_HI up to the FP32 first level of its sums
+    (the two flag tests run different ionisation kernels, which group the
+    cells of a partial sum differently: relative error of each at most 4
+    units of FP32 rounding); the autotuner writes its choice to a JSON cache under the
     device / size / dtype / ladder / group key and a second context reads it back
     without timing (the emulation's event timer reads 0 ms, so the defaults win)."""
     import json
@@ -426,7 +429,7 @@ def test_emu_launch_shapes_and_autotune_cache(tmp_path):
     pb = run.read("batchb_pk.bin", np.float64)
     np.testing.assert_allclose(pb, pa, rtol=1e-12, atol=0)
     np.testing.assert_allclose(run.read("batchb_xhi.bin", np.float64), run.read("batcha_xhi.bin", np.float64),
-                               rtol=1e-12)
+                               rtol=8 * 2.0 ** -24)
     t1 = run.read("tune1.bin", np.int32)
     assert t1[5] == 0 and t1[3] == 1 and t1[4] == 8   # timed; sorted flag test; groups up to max_walkers
     entries = json.load(open(cache))

@@ -875,10 +875,12 @@ def test_two_population_bf16_storage_with_velocity(xs):
 # ------------------------------------------------------------------ launch shapes and graphs
 
 def test_launch_shapes_and_autotune(xs, tmp_path):
-    """Launch shapes change nothing but the order of FP64 sums (the two flag tests
+    """Launch shapes change nothing but the order of sums (the two flag tests
     are exact): explicit shapes and the autotuner's choice reproduce the default
-    P(k) and mean x_HI; the choice is cached under its key and read back by a
-    second context without timing."""
+    P(k) to the order of FP64 sums and the mean x_HI to the FP32 first level of
+    its sums (the two flag tests run different ionisation kernels, which group
+    the cells of a partial sum differently); the choice is cached under its key
+    and read back by a second context without timing."""
     n, box, z, nb = 64, 128.0, 9.0, 12
     d = synth.make_box(n, box, z, seed=48, amp=AMP, dtype=np.float32)
     walkers = synth.draw_walkers(40, 17)
@@ -892,11 +894,11 @@ def test_launch_shapes_and_autotune(xs, tmp_path):
     assert not res["from_cache"] and res["best_ms"] > 0
     pk1, x1 = (t.cpu().numpy() for t in ctx.eval_batch([b], walkers))
     np.testing.assert_allclose(pk1, pk0, rtol=1e-12)
-    np.testing.assert_allclose(x1, x0, rtol=1e-12)
+    np.testing.assert_allclose(x1, x0, rtol=8 * 2.0 ** -24)
     ctx.set_tuning(n, ion_blocks=500, pipe_blocks=300, bins_blocks=700, flag_test=0, group=7)
     pk2, x2 = (t.cpu().numpy() for t in ctx.eval_batch([b], walkers))
     np.testing.assert_allclose(pk2, pk0, rtol=1e-12)
-    np.testing.assert_allclose(x2, x0, rtol=1e-12)
+    np.testing.assert_allclose(x2, x0, rtol=8 * 2.0 ** -24)
     ctx.close()
     ctx2 = _ctx(xs)
     b2 = ctx2.add_box(d, box, z, nb)
