@@ -970,15 +970,14 @@ struct IonShape {
 // that in double.
 // FIELDS: walker fw of the group also writes its x_HI and dT_b boxes (fx, fd,
 // N^3 values each) from the same per-cell values that enter its spectrum.
-// SORTED: the flag test of the whole group from the sorted tables (Eg, Pg)
-// built by k_slot_tables for the same thresholds (constant efficiency only).
-template <typename T, typename S, int N, bool TWO, bool FIELDS, bool SORTED>
+// (FP32 constant-efficiency walkers with the sorted flag test take
+// k_ion_teams below instead.)
+template <typename T, typename S, int N, bool TWO, bool FIELDS>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ odens, int nr, const WalkerConst<T>* __restrict__ wc,
     const T* __restrict__ thr, const T* __restrict__ zt, int nw, T tb, T dc, cplx<T>* __restrict__ spec,
     cplx<T>* __restrict__ nyq, double* __restrict__ xpart, const cplx<T>* __restrict__ tw, int tstride, int fw,
-    T* __restrict__ fx, T* __restrict__ fd, const T* __restrict__ Eg, const uint64_t* __restrict__ Pg) {
-  static_assert(!(SORTED && TWO), "the sorted flag test covers one-sided thresholds only");
+    T* __restrict__ fx, T* __restrict__ fd) {
   using IS = IonShape<N>;
   constexpr size_t N3 = static_cast<size_t>(N) * N * N;
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
@@ -992,26 +991,14 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
   const int lane = t & 63;
   const int row = t / N, x = t % N;
   T* ldsr = reinterpret_cast<T*>(lds);
-  // SORTED: the search trees of the group's slots, E[nr][64], at a fixed LDS
-  // address (so that the search's reads fold it into their offsets)
-  __shared__ T El[SORTED ? kNrMax * kSortWidth : 1];
-  if constexpr (SORTED)
-    for (int e = t; e < (nr + 3) / 4 * 4 * kSortWidth; e += IS::NT) El[e] = Eg[e];
   for (int w = t; w < kMaxGroup; w += IS::NT) acc[w] = 0.0;
   load_twiddles<N>(twl, tw, tstride);
   const T tbh = T(0.5) * tb;
   for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
     const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
-    // ballot test: every slot's delta_R in registers for the walker loop;
-    // sorted test: the cell's walker mask first, then only the cell radius
-    T d[SORTED ? 1 : kNrMax];
-    uint32_t mlo = 0, mhi = 0;
-    if constexpr (SORTED) {
-      sorted_flags<T, S>(dR, N3, cell, nr, El, Pg, mlo, mhi);
-      d[0] = load_as<T>(dR, static_cast<size_t>(nr - 1) * N3 + cell);
-    } else {
-      load_radii<T, S>(dR, N3, cell, nr, d);
-    }
+    // every slot's delta_R in registers for the walker loop
+    T d[kNrMax];
+    load_radii<T, S>(dR, N3, cell, nr, d);
     const T od = odens[cell];
     const T u = dc - d[0];   // argument of the partial ionisation, per cell
     const T u2 = u * u;
@@ -1020,29 +1007,15 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
     // the first walker, keeps one load-counter wait per radius inside the loop
     // for every walker (an empty asm taking the values, no instruction).
 #pragma unroll
-    for (int s = 0; s < (SORTED ? 1 : kNrMax); ++s) asm volatile("" ::"v"(d[s]));
+    for (int s = 0; s < kNrMax; ++s) asm volatile("" ::"v"(d[s]));
     for (int w0 = 0; w0 < nw; w0 += IS::WB) {
       const int qn = min(IS::WB, nw - w0);  // walkers in this batch; later slots are not written out
-      // SORTED: the batch's walkers' bits of the cell's mask, from bit 0 (a
-      // batch lies within one 32-walker half)
-      const uint32_t mb = (w0 < 32 ? mlo : mhi) >> (w0 & 31);
 #pragma unroll 1
       for (int q = 0; q < qn; ++q) {
         const int w = w0 + q;
-        T xh;
-        if constexpr (SORTED) {
-          static_assert(32 % IS::WB == 0, "a walker batch must lie within one half of the mask");
-          const WalkerConst<T> c = load_walker(wc + w);
-          xh = T(1);
-          if ((mb >> q) & 1u)
-            xh = T(0);
-          else if (c.partial)
-            xh = partial_xhi(c, u, u2);
-        } else {
-          xh = cell_xhi<T, (SORTED ? 1 : kNrMax), TWO>(d, load_walker(wc + w),
-                                                       thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
-                                                       zt + static_cast<size_t>(w) * kZetaPitch, dc, u2);
-        }
+        const T xh = cell_xhi<T, kNrMax, TWO>(d, load_walker(wc + w),
+                                              thr + static_cast<size_t>(w) * (TWO ? 2 : 1) * kNrMax,
+                                              zt + static_cast<size_t>(w) * kZetaPitch, dc, u2);
         // dT_b at half scale (tbh = tb / 2): the unpacking after the
         // transform then needs no halving, with bitwise the same spectrum
         const T tvh = tbh * xh * od;
@@ -1178,8 +1151,11 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
     }
     __syncthreads();
     for (int w0 = 0; w0 < nw; w0 += WB) {
-      // teams past the group's end repeat its last walker and store nothing
-      // (every lane keeps to the wave-level synchronisation)
+      // waves whose teams all lie past the group's end skip the batch (a
+      // wave-uniform branch); in a wave with a live team, teams past the end
+      // repeat the group's last walker and store nothing, keeping to the
+      // wave-level synchronisation
+      if (w0 + (t & ~63) / TS >= nw) continue;
       const int w = min(w0 + q, nw - 1);
       const bool live = w0 + q < nw;
       const WalkerConst<T> c = load_walker(wc + w);
@@ -1732,20 +1708,18 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
         T* E = static_cast<T*>(slot_tab);
         uint64_t* P = reinterpret_cast<uint64_t*>(static_cast<unsigned char*>(slot_tab) +
                                                   static_cast<size_t>(kNrMax) * kSortWidth * sizeof(double));
-        auto go = [&](auto two, auto withf, auto srt) {
-          constexpr bool SRT = decltype(srt)::value && !decltype(two)::value && std::is_same<T, float>::value;
-          hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value, decltype(withf)::value, SRT>),
+        auto go = [&](auto two, auto withf) {
+          hipLaunchKernelGGL((k_ion_rows<T, ST, N, decltype(two)::value, decltype(withf)::value>),
                              dim3(ion_grid(N, blocks)), dim3(IonShape<N>::NT), 0, s, static_cast<const ST*>(dR),
                              static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc),
                              static_cast<const T*>(thr), static_cast<const T*>(zt), nw, static_cast<T>(tb),
                              static_cast<T>(dc), static_cast<cplx<T>*>(spec), static_cast<cplx<T>*>(nyq), xpart,
                              static_cast<const cplx<T>*>(tw), ntab / N, field_walker, static_cast<T*>(x_hi),
-                             static_cast<T*>(dtb), static_cast<const T*>(E), static_cast<const uint64_t*>(P));
+                             static_cast<T*>(dtb));
           return hipGetLastError();
         };
-        if (zt) return fields ? go(std::true_type{}, std::true_type{}, std::false_type{})
-                              : go(std::true_type{}, std::false_type{}, std::false_type{});
-        if (sorted) {
+        if (zt) return fields ? go(std::true_type{}, std::true_type{}) : go(std::true_type{}, std::false_type{});
+        if (sorted) {   // FP32 only (see `sorted` above)
           hipLaunchKernelGGL((k_slot_tables<T>), dim3(static_cast<unsigned>(kNrMax)), dim3(kSortWidth), 0, s,
                              static_cast<const T*>(thr), nw, E, P);
           hipError_t e = hipGetLastError();
@@ -1763,11 +1737,8 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
             };
             return fields ? teams(std::true_type{}) : teams(std::false_type{});
           }
-          return fields ? go(std::false_type{}, std::true_type{}, std::true_type{})
-                        : go(std::false_type{}, std::false_type{}, std::true_type{});
         }
-        return fields ? go(std::false_type{}, std::true_type{}, std::false_type{})
-                      : go(std::false_type{}, std::false_type{}, std::false_type{});
+        return fields ? go(std::false_type{}, std::true_type{}) : go(std::false_type{}, std::false_type{});
       });
     });
   });
