@@ -194,10 +194,16 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_r2c(const T* __restric
 // ---------------------------------------------------------------------------
 // Inverse rows: half spectra [rows][N/2+1] -> real [rows][N] * scale, stored as S,
 // for a batch of smoothing radii.  Items g = radius * groups + group of WB row
-// pairs form a grid-stride loop; the loads of a block's next item are issued
-// into registers before the FFT and stores of the current one.  Radius r reads
-// in + r istride, writes out + r ostride (streaming stores) and only reads
-// entries kx <= kmax(r) (the rest are zero after its sharp-k cut).
+// pairs form a grid-stride loop.  Each row pair is packed into one complex
+// row Z = A + i B and transformed by one team (TS threads within one wave):
+// member j reads the entries k = j + r TS of its row (index min(k, N - k) of
+// the two half spectra), which are exactly its first-stage butterfly, so that
+// stage runs in registers; the remaining stages and the stores are the
+// team's own (wave-level synchronisation only, no block barrier).  The loads
+// of a block's next item are issued into registers right after the first
+// stage.  Radius r reads in + r istride, writes out + r ostride (streaming
+// stores) and only reads entries kx <= kmax(r) (the rest are zero after its
+// sharp-k cut).
 // ---------------------------------------------------------------------------
 template <typename T, typename ST, int N>
 __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __restrict__ in, ST* __restrict__ out,
@@ -206,65 +212,65 @@ __global__ __launch_bounds__(RowShape<N>::NT) void k_rows_c2r(const cplx<T>* __r
                                                               long ostride, const cplx<T>* __restrict__ tw,
                                                               int tstride) {
   using S = RowShape<N>;
+  constexpr int TS = S::TS, R0 = FftShape<N, typename S::Plan>::R0;
+  static_assert(N / R0 == TS && S::WB * TS == S::NT, "one packed row per team");
   __shared__ cplx<T> lds[S::WB * N];
   __shared__ cplx<T> twl[N];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, q = t / TS, j = t % TS;
   const long groups = (npairs + S::WB - 1) / S::WB;
   load_twiddles<N>(twl, tw, tstride);
-  // this thread builds entry k = t of every packed row: it reads index
-  // idx = min(k, N - k) of the two half spectra
-  const int idx = t <= N / 2 ? t : N - t;
-  cplx<T> pa[S::WB], pb[S::WB];
+  cplx<T>* my = lds + q * N;   // the team's packed row
+  cplx<T> pa[R0], pb[R0];
   const auto load = [&](long g) {
-    const long r = g / groups, p0 = (g % groups) * S::WB;
-    const bool live = idx <= cut[2 * r + 1];
-    const cplx<T>* src = in + r * istride;
+    const long r = g / groups;
+    const long p = min((g % groups) * S::WB + q, npairs - 1);  // a valid row; rows past the end are not stored
+    const long kc = cut[2 * r + 1];
+    const cplx<T>* sa = in + r * istride + (2 * p) * S::HP;
 #pragma unroll
-    for (int q = 0; q < S::WB; ++q) {
-      pa[q] = {T(0), T(0)};
-      pb[q] = {T(0), T(0)};
-    }
-    if (live) {
-#pragma unroll
-      for (int q = 0; q < S::WB; ++q) {
-        const long p = min(p0 + q, npairs - 1);  // a valid row; rows past the end are not stored
-        pa[q] = src[(2 * p) * S::HP + idx];
-        pb[q] = src[(2 * p + 1) * S::HP + idx];
+    for (int e = 0; e < R0; ++e) {
+      const int k = j + e * TS;
+      const int idx = k <= N / 2 ? k : N - k;
+      pa[e] = {T(0), T(0)};
+      pb[e] = {T(0), T(0)};
+      if (idx <= kc) {
+        pa[e] = sa[idx];
+        pb[e] = sa[S::HP + idx];
       }
     }
   };
   long g = blockIdx.x;
   if (g < nitems) load(g);
   for (; g < nitems; g += gridDim.x) {
+    const long r = g / groups, p = (g % groups) * S::WB + q;
     // Z[k] = A[k] + i B[k] (Hermitian extension; DC and Nyquist taken as real)
+    cplx<T> v[R0];
 #pragma unroll
-    for (int q = 0; q < S::WB; ++q) {
-      cplx<T> A = pa[q], B = pb[q];
-      if (t == 0 || t == N / 2) {
+    for (int e = 0; e < R0; ++e) {
+      const int k = j + e * TS;
+      cplx<T> A = pa[e], B = pb[e];
+      if (k == 0 || k == N / 2) {
         A.y = T(0);
         B.y = T(0);
-      } else if (t > N / 2) {
+      } else if (k > N / 2) {
         A = cconj(A);
         B = cconj(B);
       }
-      lds[q * N + t] = {A.x - B.y, A.y + B.x};
+      v[e] = {A.x - B.y, A.y + B.x};
     }
-    __syncthreads();
-    const long r = g / groups, p0 = (g % groups) * S::WB;
+    fft_first_from_regs<N, +1, T, typename S::Plan>(v, my, 1, j);
     if (g + gridDim.x < nitems) load(g + gridDim.x);
-    fft_team<N, +1, T, typename S::Plan, true>(lds + (t / S::TS) * N, 1, t % S::TS, twl, 1);
-    __syncthreads();   // the row teams synchronised only within their waves
-    ST* dst = out + r * ostride;
+    fft_rest<N, +1, T, typename S::Plan, true>(my, 1, j, twl, 1);
+    if (p < npairs) {
+      ST* dst = out + r * ostride;
 #pragma unroll
-    for (int q = 0; q < S::WB; ++q) {
-      const long p = p0 + q;
-      if (p < npairs) {
-        const cplx<T> v = lds[q * N + t];
-        store_as_stream(dst, (2 * p) * N + t, v.x * scale);
-        store_as_stream(dst, (2 * p + 1) * N + t, v.y * scale);
+      for (int e = 0; e < R0; ++e) {
+        const int n = j + e * TS;
+        const cplx<T> z = my[n];
+        store_as_stream(dst, (2 * p) * N + n, z.x * scale);
+        store_as_stream(dst, (2 * p + 1) * N + n, z.y * scale);
       }
     }
-    __syncthreads();
+    stage_sync<true>();   // the team's row is read before the next item writes it
   }
 }
 
