@@ -703,9 +703,13 @@ __device__ __forceinline__ unsigned long long flag_mask(const T (&d)[NR], int ch
 // (the cell-radius threshold lies below delta_c), which takes the erfc of a
 // positive argument with the cell's u and u^2 formed once for all walkers.
 template <typename T>
+__device__ __forceinline__ T partial_xhi_pos(const WalkerConst<T>& c, T u, T u2) {
+  return T(1) - c.zeta * erfc_pos(c.ha, c.a2l, u, u2);
+}
+template <typename T>
 __device__ __forceinline__ T partial_xhi(const WalkerConst<T>& c, T u, T u2) {
   if constexpr (sizeof(T) == 4) {
-    if (c.partial == 2) return T(1) - c.zeta * erfc_pos(c.ha, c.a2l, u, u2);
+    if (c.partial == 2) return partial_xhi_pos(c, u, u2);
   }
   return T(1) - c.zeta * erfc_t(c.a_cell * u);
 }
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
     // every slot's delta_R in registers for the walker loop
     T d[kNrMax];
     load_radii<T, S>(dR, N3, cell, nr, d);
-    const T od = odens[cell];
+    const T odh = tbh * odens[cell];   // dT_b per unit x_HI, at half scale
     const T u = dc - d[0];   // argument of the partial ionisation, per cell
     const T u2 = u * u;
     // Every delta_R of the cell is in its register before the walker loop:
@@ -1024,12 +1028,12 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void
                                               zt + static_cast<size_t>(w) * kZetaPitch, dc, u2);
         // dT_b at half scale (tbh = tb / 2): the unpacking after the
         // transform then needs no halving, with bitwise the same spectrum
-        const T tvh = tbh * xh * od;
+        const T tvh = xh * odh;
         ldsr[2 * (q * N + x) + row] = tvh;
         if constexpr (FIELDS) {
           if (w == fw) {
             fx[cell] = xh;
-            fd[cell] = tvh + tvh;   // exactly tb xh od
+            fd[cell] = tvh + tvh;   // dT_b at full scale (doubling is exact)
           }
         }
         if constexpr (IS::NT >= 64) {
@@ -1132,7 +1136,8 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
   __shared__ cplx<T> twl[N];
   __shared__ T El[kNrMax * kSortWidth];
   // per cell of the row pair: walker mask halves (walkers 0..31, 32..63),
-  // u = delta_c - delta_cell and (1 + delta) times the velocity factor
+  // u = delta_c - delta_cell and dT_b per unit x_HI at half scale, tb / 2
+  // times (1 + delta) times the velocity factor
   __shared__ uint32_t cmask[2][NT];
   __shared__ T cu[NT], cod[NT];
   __shared__ double acc[kMaxGroup];
@@ -1144,6 +1149,51 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
   load_twiddles<N>(twl, tw, tstride);
   const T tbh = T(0.5) * tb;   // dT_b at half scale: the unpacking needs no halving
   cplx<T>* my = lds + q * N;   // the team's packed row
+  // the walker's dT_b at half scale of the team's cells (x = j + r TS of rows
+  // 2p and 2p + 1), their packed row's entries, and its x_HI sum per thread;
+  // PARTIAL: 2 when every walker of the wave takes the erfc form of the
+  // partial ionisation (no per-cell branch on the form), -1 otherwise
+  const auto cells = [&](auto partial, const WalkerConst<T>& c, const uint32_t* cm, uint32_t bit, bool live,
+                         int w, long p, cplx<T> (&v)[R0], T (&xs)[R0]) {
+    constexpr int PARTIAL = decltype(partial)::value;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int xx = j + r * TS;
+      T xh2[2], tv2[2];
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        const int e = rr * N + xx;
+        const T u = cu[e];
+        T xh;
+        if constexpr (PARTIAL == 2) {
+          xh = T(0);
+          if (!(cm[e] & bit)) xh = partial_xhi_pos(c, u, u * u);
+        } else {
+          xh = T(1);
+          if (cm[e] & bit)
+            xh = T(0);
+          else if (c.partial)
+            xh = partial_xhi(c, u, u * u);
+        }
+        xh2[rr] = xh;
+        tv2[rr] = xh * cod[e];
+        if constexpr (FIELDS) {
+          if (live && w == fw) {
+            const size_t cell = static_cast<size_t>(2 * p + rr) * N + xx;
+            fx[cell] = xh;
+            fd[cell] = tv2[rr] + tv2[rr];   // dT_b at full scale (doubling is exact)
+          }
+        }
+      }
+      // dT_b rounded before the transform, as k_ion_rows stores it (no
+      // multiply-add contraction into the first butterfly): the spectra
+      // of the two kernels are bitwise equal
+      in_vgpr(tv2[0]);
+      in_vgpr(tv2[1]);
+      v[r] = {tv2[0], tv2[1]};
+      xs[r] = xh2[0] + xh2[1];
+    }
+  };
   for (long p = blockIdx.x; p < static_cast<long>(N) * N / 2; p += gridDim.x) {
     {
       const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
@@ -1153,7 +1203,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
       cmask[0][t] = mlo;
       cmask[1][t] = mhi;
       cu[t] = dc - d0;
-      cod[t] = odens[cell];
+      cod[t] = tbh * odens[cell];
     }
     __syncthreads();
     for (int w0 = 0; w0 < nw; w0 += WB) {
@@ -1169,37 +1219,11 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
       const uint32_t bit = 1u << (w & 31);
       cplx<T> v[R0];
       T xs[R0];
-#pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        const int xx = j + r * TS;
-        T xh2[2], tv2[2];
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-          const int e = rr * N + xx;
-          const T u = cu[e];
-          T xh = T(1);
-          if (cm[e] & bit)
-            xh = T(0);
-          else if (c.partial)
-            xh = partial_xhi(c, u, u * u);
-          xh2[rr] = xh;
-          tv2[rr] = tbh * xh * cod[e];
-          if constexpr (FIELDS) {
-            if (live && w == fw) {
-              const size_t cell = static_cast<size_t>(2 * p + rr) * N + xx;
-              fx[cell] = xh;
-              fd[cell] = tv2[rr] + tv2[rr];   // exactly tb xh od
-            }
-          }
-        }
-        // dT_b rounded before the transform, as k_ion_rows stores it (no
-        // multiply-add contraction into the first butterfly): the spectra
-        // of the two kernels are bitwise equal
-        in_vgpr(tv2[0]);
-        in_vgpr(tv2[1]);
-        v[r] = {tv2[0], tv2[1]};
-        xs[r] = xh2[0] + xh2[1];
-      }
+      // a wave-uniform choice of the per-cell form
+      if (__ballot(c.partial != 2) == 0)
+        cells(std::integral_constant<int, 2>{}, c, cm, bit, live, w, p, v, xs);
+      else
+        cells(std::integral_constant<int, -1>{}, c, cm, bit, live, w, p, v, xs);
       // the walker's x_HI partial sum: pairwise over the thread's values, then the team
 #pragma unroll
       for (int h = R0 / 2; h >= 1; h /= 2)
