@@ -122,6 +122,23 @@ __host__ __device__ __forceinline__ WalkerConst<T> load_walker(const WalkerConst
   return c;
 }
 
+// The fields of the partial ionisation alone (zeta, a_cell, partial, ha, a2l;
+// the others zero), in loads whose every register is used: a load left in
+// flight across other work then holds no dead register that the compiler
+// would hand to other values (and so wait for the load early).
+__device__ __forceinline__ WalkerConst<float> load_walker_partial(const WalkerConst<float>* p) {
+  typedef float F2 __attribute__((vector_size(8)));
+  WalkerConst<float> c{};
+  const F2 za = *reinterpret_cast<const F2*>(&p->zeta);
+  const F2 h = *reinterpret_cast<const F2*>(&p->ha);
+  c.zeta = za[0];
+  c.a_cell = za[1];
+  c.partial = p->partial;
+  c.ha = h[0];
+  c.a2l = h[1];
+  return c;
+}
+
 // Two-population efficiency of eq. (9): radius-slot constants (walker
 // independent) and walker inputs of the device planning pass, FP64.
 struct SlotPlan2 {

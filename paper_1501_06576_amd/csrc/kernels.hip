@@ -1149,11 +1149,28 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
   load_twiddles<N>(twl, tw, tstride);
   const T tbh = T(0.5) * tb;   // dT_b at half scale: the unpacking needs no halving
   cplx<T>* my = lds + q * N;   // the team's packed row
+  // the team's walker in the batch starting at w0 (teams past the group's end
+  // repeat its last walker)
+  const auto walker_of = [&](int w0) { return min(w0 + q, nw - 1); };
+  // The constants of the wave's TPW walkers are scalar loads (a wave-uniform
+  // address), one batch ahead (the batch after a row pair's last is the next
+  // row pair's first): their wait then counts no vector memory operation, so
+  // that it does not wait for the previous batch's stores.  Each team then
+  // takes its own walker's fields.
+  constexpr int TPW = (NT < 64 ? NT : 64) / TS;   // teams per wave
+  const int qw = __builtin_amdgcn_readfirstlane(q - q % TPW);   // the wave's first team
+  const int qi = q % TPW;
+  WalkerConst<T> cw[TPW];
+  const auto load_wave = [&](int w0) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) cw[i] = load_walker_partial(wc + min(w0 + qw + i, nw - 1));
+  };
+  load_wave(0);
   // the walker's dT_b at half scale of the team's cells (x = j + r TS of rows
   // 2p and 2p + 1), their packed row's entries, and its x_HI sum per thread;
   // PARTIAL: 2 when every walker of the wave takes the erfc form of the
   // partial ionisation (no per-cell branch on the form), -1 otherwise
-  const auto cells = [&](auto partial, const WalkerConst<T>& c, const uint32_t* cm, uint32_t bit, bool live,
+  const auto cells = [&](auto partial, const WalkerConst<T>& cw, const uint32_t* cm, uint32_t bit, bool live,
                          int w, long p, cplx<T> (&v)[R0], T (&xs)[R0]) {
     constexpr int PARTIAL = decltype(partial)::value;
 #pragma unroll
@@ -1167,13 +1184,13 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
         T xh;
         if constexpr (PARTIAL == 2) {
           xh = T(0);
-          if (!(cm[e] & bit)) xh = partial_xhi_pos(c, u, u * u);
+          if (!(cm[e] & bit)) xh = partial_xhi_pos(cw, u, u * u);
         } else {
           xh = T(1);
           if (cm[e] & bit)
             xh = T(0);
-          else if (c.partial)
-            xh = partial_xhi(c, u, u * u);
+          else if (cw.partial)
+            xh = partial_xhi(cw, u, u * u);
         }
         xh2[rr] = xh;
         tv2[rr] = xh * cod[e];
@@ -1211,16 +1228,26 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
       // wave-uniform branch); in a wave with a live team, teams past the end
       // repeat the group's last walker and store nothing, keeping to the
       // wave-level synchronisation
-      if (w0 + (t & ~63) / TS >= nw) continue;
-      const int w = min(w0 + q, nw - 1);
+      const int wn0 = w0 + WB < nw ? w0 + WB : 0;   // the next batch
+      if (w0 + qw >= nw) {
+        load_wave(wn0);
+        continue;
+      }
+      const int w = walker_of(w0);
       const bool live = w0 + q < nw;
-      const WalkerConst<T> c = load_walker(wc + w);
       const uint32_t* cm = cmask[w0 < 32 ? 0 : 1];   // a batch lies within one half
       const uint32_t bit = 1u << (w & 31);
       cplx<T> v[R0];
       T xs[R0];
+      WalkerConst<T> c = cw[0];
+#pragma unroll
+      for (int i = 1; i < TPW; ++i)
+        if (qi == i) c = cw[i];
       // a wave-uniform choice of the per-cell form
-      if (__ballot(c.partial != 2) == 0)
+      bool all2 = true;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) all2 = all2 && cw[i].partial == 2;
+      if (all2)
         cells(std::integral_constant<int, 2>{}, c, cm, bit, live, w, p, v, xs);
       else
         cells(std::integral_constant<int, -1>{}, c, cm, bit, live, w, p, v, xs);
@@ -1234,6 +1261,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
       // the packed row's transform, the team alone
       fft_first_from_regs<N, -1, T, typename IS::Plan>(v, my, 1, j);
       fft_rest<N, -1, T, typename IS::Plan, true>(my, 1, j, twl, 1);
+      load_wave(wn0);   // in flight during the unpacking and stores
       if (live) {
         cplx<T>* o = spec + static_cast<size_t>(w) * SPEC + static_cast<size_t>(2 * p) * IS::HP;
 #pragma unroll

@@ -121,6 +121,8 @@ inline int __builtin_amdgcn_readlane(int v, int lane) {
   ::hipemu::wave_exchange(&v, &r, sizeof(int), lane);
   return r;
 }
+// every lane of the wave calls it with all lanes active: lane 0 is the first
+inline int __builtin_amdgcn_readfirstlane(int v) { return __builtin_amdgcn_readlane(v, 0); }
 inline int __float_as_int(float f) { return __builtin_bit_cast(int, f); }
 inline float __int_as_float(int i) { return __builtin_bit_cast(float, i); }
 inline float __fdividef(float a, float b) { return a / b; }
