@@ -96,16 +96,29 @@ struct AxisShape {
   static constexpr int NT = TI * TS;
 };
 
-// Threads of the binning pass: the strided passes' FFT teams over at most
-// kBinsTileCols columns per tile (and at most the strided passes' TI), but
-// never fewer than one wave per block (the final reduction runs one wave per
-// bin).  At 256^3, 8 columns (64-byte segments, 256-thread blocks, 5 blocks
-// per CU) measured 4 % faster than 16 (512-thread blocks, 2 per CU).
+// Radix plan of the binning pass: the strided passes' plan, except at N =
+// 256, where a 16 x 16 plan (teams of 16 threads) fits 16 columns, i.e.
+// whole 128-byte lines of FP32 modes, in a 256-thread block.
+template <int N>
+struct BinPlan {
+  using type = typename AxisPlan<N>::type;
+};
+template <>
+struct BinPlan<256> {
+  using type = FftPlan<256>;
+};
+
+// Threads of the binning pass: FFT teams over as many columns per tile as
+// kBinsTileCols columns of the strided passes' teams take threads (and at
+// most the strided passes' TI), but never fewer than one wave per block (the
+// final reduction runs one wave per bin).
 template <int N>
 struct BinShape {
-  using Plan = typename AxisShape<N>::Plan;
-  static constexpr int TS = AxisShape<N>::TS;
-  static constexpr int TIA = AxisShape<N>::TI < kBinsTileCols ? AxisShape<N>::TI : kBinsTileCols;
+  using Plan = typename BinPlan<N>::type;
+  static constexpr int TS = FftShape<N, Plan>::TS;
+  static constexpr int TIW = AxisShape<N>::TI < kBinsTileCols ? AxisShape<N>::TI : kBinsTileCols;
+  static constexpr int TIS = TIW * AxisShape<N>::TS / TS;
+  static constexpr int TIA = TIS < AxisShape<N>::TI ? TIS : AxisShape<N>::TI;
   static constexpr int TI = TIA * TS >= 64 ? TIA : 64 / TS;
   static constexpr int NT = TI * TS;
   // Tiles per 16-column group: with 8-column tiles, the two halves of each
@@ -473,8 +486,8 @@ __global__ __launch_bounds__(AxisShape<N>::NT) void k_axis_pipe(const cplx<T>* s
 // x- and y-transformed spectra (padded rows, kx < N/2) and nyq [outer][N][N]
 // their Nyquist planes kx = N/2 as [ky][z].  Tiles cover live columns only
 // and keep aligned loads: "main" tiles are TI consecutive kx < KM of one y
-// (KM = the largest multiple of TI <= N/2; TI = 8 at N = 256, 64-byte
-// segments), "rest" tiles gather the remaining columns (kx in [KM, N/2], the
+// (KM = the largest multiple of TI <= N/2; TI = 16 at N = 256, whole
+// 128-byte lines), "rest" tiles gather the remaining columns (kx in [KM, N/2], the
 // Nyquist plane for N >= 32) of TI consecutive (y, kx) pairs.  Block i of a
 // spectrum's `parts` blocks takes the groups i, i + parts, i + 2 parts, ... of
 // G consecutive entries of the list `tiles` (BinShape::G; blocks running
