@@ -1120,8 +1120,10 @@ __device__ __forceinline__ T team_sum(T v) {
 // walkers with the sorted flag test, organised around the x-pass FFT teams.
 // Per row pair (rows 2p, 2p+1; one cell per thread) the block first finds
 // each cell's walker mask (sorted_flags) and keeps it with u = delta_c -
-// delta_cell and (1 + delta) in LDS.  Then for each batch of WB walkers, team
-// q (TS consecutive threads, within one wave) takes walker w0 + q: member j
+// delta_cell and dT_b per unit x_HI in LDS.  Then for each batch of WB
+// walkers, team q (TS consecutive threads, within one wave) takes walker
+// w0 + q (the constants of a wave's walkers are scalar loads, one batch
+// ahead): member j
 // forms the packed row's elements j + r TS (r < R0) — the cells x = j + r TS
 // of both rows — which are exactly its first-stage butterfly, so that stage
 // runs in registers; the remaining stages, the unpacking into the half

@@ -75,9 +75,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const F4* __restri
 // segment kx in [16 c, 16 c + 16) of row (z, y) for all N values of z (every
 // segment of the padded rows, so the whole buffer is read once; blocks
 // running together read neighbouring segments); the block's 256 threads read
-// 16 z-planes x 16 complex values per step.  (The pass itself reads 64-byte
-// halves of these lines from neighbouring blocks; as a probe that pattern
-// measured slower than the pass, so the whole-line form is the ceiling.)
+// 16 z-planes x 16 complex values per step, as the pass does at N = 256.
 constexpr int kTileN = 256;
 constexpr int kTileHP = 144;
 constexpr int kTileSeg = 16;   // complex values per 128-byte segment
