@@ -226,11 +226,12 @@ def test_smoothed_boxes(xs):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype,n", [("f64", 32), ("f32", 64), ("f32", 16)])
+@pytest.mark.parametrize("dtype,n", [("f64", 32), ("f32", 64), ("f32", 16), ("f64", 256)])
 def test_power_spectrum_plane_wave(xs, dtype, n):
-    """A single plane wave puts a^2 L^3 / (2 c_b) into its own bin and nothing elsewhere."""
+    """A single plane wave puts a^2 L^3 / (2 c_b) into its own bin and nothing elsewhere
+    (FP64 at 256^3: the binning pass's 16 x 16 plan with FP64 tiles and slots)."""
     import torch
-    box, nb, amp = 50.0, 6, 1.7
+    box, nb, amp = (50.0 if n <= 64 else 250.0), 6, 1.7   # 250 Mpc keeps the 256^3 ladder within 40 radii
     m = (1, 2, 3) if n > 16 else (1, 0, 2)
     g = np.indices((n, n, n))
     f = amp * np.cos(2 * np.pi * (m[0] * g[0] + m[1] * g[1] + m[2] * g[2]) / n)
