@@ -392,8 +392,9 @@ typedef struct {
   int32_t ion_blocks;   /* blocks of the ionisation pass, <= 16384 (default 8192, or n^2/2 if fewer) */
   int32_t pipe_blocks;  /* blocks of the pipelined strided passes and smoothing rows (default 2048) */
   int32_t bins_blocks;  /* blocks of one binning launch over a walker group (default 2048) */
-  int32_t flag_test;    /* FP32 boxes, constant efficiency: 1 sorted-threshold search per radius
-                           for the whole walker group, 0 one compare per walker and radius */
+  int32_t flag_test;    /* FP32 boxes: 1 sorted-threshold search per radius for the whole walker
+                           group (two for two-population walkers: lower and upper interval
+                           ends), 0 one compare per walker and radius (two for intervals) */
   int32_t group;        /* walkers per ionisation launch, <= 64 and <= max_walkers (default min of both) */
 } xs21_tuning;
 

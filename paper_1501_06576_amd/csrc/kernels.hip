@@ -780,17 +780,25 @@ constexpr int kSortWidth = 64;   // walkers per sorted group (= kMaxGroup)
 constexpr int kMaskPitch = 66;   // prefix masks per slot (65 used), 16-byte rows
 static_assert(kSortWidth == kMaxGroup, "one sorted table covers one walker group");
 
-// Tables of slots [0, gridDim.x) for walkers [0, nw) with thresholds
-// thr[w][kNrMax] (slot index as in the ionisation pass).  One block of 64
-// threads per slot; thread w ranks walker w's threshold (ties by index).
+// Tables of slots [0, kNrMax) for walkers [0, nw) with thresholds
+// thr[w * wstride + s] (slot index as in the ionisation pass).  One block of
+// 64 threads per slot; thread w ranks walker w's threshold (ties by index).
+// Blocks kNrMax .. 2 kNrMax - 1 (two-population walkers, wstride = 2 kNrMax)
+// build the second set, E + kNrMax * kSortWidth and P + kNrMax * kMaskPitch,
+// from the upper ends thr[w * wstride + kNrMax + s], each raised to the next
+// float: hi < delta_R iff nextup(hi) <= delta_R, so that the same search
+// counts the walkers whose interval ends below delta_R.
 template <typename T>
-__global__ __launch_bounds__(kSortWidth) void k_slot_tables(const T* __restrict__ thr, int nw, T* __restrict__ E,
-                                                            uint64_t* __restrict__ P) {
-  const int s = blockIdx.x, w = threadIdx.x;
+__global__ __launch_bounds__(kSortWidth) void k_slot_tables(const T* __restrict__ thr, int wstride, int nw,
+                                                            T* __restrict__ E, uint64_t* __restrict__ P) {
+  const int s = blockIdx.x % kNrMax, h = blockIdx.x / kNrMax, w = threadIdx.x;
   __shared__ T v[kSortWidth];
   __shared__ T srt[kSortWidth];
   __shared__ int id[kSortWidth];
-  const T mine = w < nw ? thr[static_cast<size_t>(w) * kNrMax + s] : static_cast<T>(INFINITY);
+  T mine = w < nw ? thr[static_cast<size_t>(w) * wstride + h * kNrMax + s] : static_cast<T>(INFINITY);
+  if (h == 1) mine = nextafter(mine, static_cast<T>(INFINITY));
+  E += static_cast<size_t>(h) * kNrMax * kSortWidth;
+  P += static_cast<size_t>(h) * kNrMax * kMaskPitch;
   v[w] = mine;
   __syncthreads();
   int r = 0;
@@ -858,9 +866,13 @@ __device__ __forceinline__ int heap_step(int H, double e, double d, int s0, int 
 // complete early.  The four searches of a group run level by level, so their
 // LDS reads issue together, and the mask reads of a group are consumed only
 // after the next group's searches.  Loads address a slot's plane (or mask
-// row) from scalars plus one 32-bit offset per lane.  Returns bits 0..31 in
-// lo and 32..63 in hi.
-template <typename T, typename S>
+// row) from scalars plus one 32-bit offset per lane.  TWO (two-population
+// intervals): a second set of tables (E + kNrMax * kSortWidth, P + kNrMax *
+// kMaskPitch) of the upper ends raised to the next float gives per slot the
+// walkers whose interval ends below delta_R, which that slot does not flag:
+// the slot's mask is P_lo[k_lo] & ~P_hi[k_hi].  Returns bits 0..31 in lo and
+// 32..63 in hi.
+template <typename T, typename S, bool TWO = false>
 __device__ __forceinline__ void sorted_flags(const S* __restrict__ dR, size_t n3, size_t cell, int nr, const T* E,
                                              const uint64_t* __restrict__ P, uint32_t& lo, uint32_t& hi) {
   constexpr int GS = 4;
@@ -880,7 +892,7 @@ __device__ __forceinline__ void sorted_flags(const S* __restrict__ dR, size_t n3
   T dn[GS];
 #pragma unroll
   for (int j = 0; j < GS; ++j) dn[j] = ld(j);
-  uint64_t acc = 0, pend[GS] = {0, 0, 0, 0};
+  uint64_t acc = 0, pend[GS] = {0, 0, 0, 0}, pendh[GS] = {0, 0, 0, 0};
   const unsigned char* eb = reinterpret_cast<const unsigned char*>(E);
   // a rolled loop: unrolled, the compiler keeps every slot's base address live
   // across the cell loop (and spills them)
@@ -902,42 +914,62 @@ __device__ __forceinline__ void sorted_flags(const S* __restrict__ dR, size_t n3
     int step0 = SZ - G, step1 = 2 * SZ - G;
     in_vgpr(step0);   // in registers: the select reads VCC, its one scalar operand
     in_vgpr(step1);
-    int H[GS];
+    // the search of table tb (0: the thresholds, 1: the raised upper ends of
+    // two-population intervals) and its mask reads
+    const auto search = [&](auto tbc, uint64_t (&cur)[GS]) {
+      constexpr int TB = decltype(tbc)::value;
+      const unsigned char* ebt = eb + TB * kNrMax * TREE;
+      int H[GS];
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-      H[j] = G;
-      in_vgpr(H[j]);
-    }
+      for (int j = 0; j < GS; ++j) {
+        H[j] = G;
+        in_vgpr(H[j]);
+      }
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      T e[GS];
+      for (int l = 0; l < 6; ++l) {
+        T e[GS];
 #pragma unroll
-      for (int j = 0; j < GS; ++j) e[j] = *reinterpret_cast<const T*>(eb + j * TREE + H[j]);
+        for (int j = 0; j < GS; ++j) e[j] = *reinterpret_cast<const T*>(ebt + j * TREE + H[j]);
 #pragma unroll
-      for (int j = 0; j < GS; ++j) H[j] = heap_step(H[j], e[j], dv[j], step0, step1);
-    }
+        for (int j = 0; j < GS; ++j) H[j] = heap_step(H[j], e[j], dv[j], step0, step1);
+      }
+#pragma unroll
+      for (int j = 0; j < GS; ++j) {
+        // h = 64 + k, k in [0, 63], so H - G = SZ (63 + k) < GS TREE and G is a
+        // multiple of GS TREE: S_63 (E[63] of the slot) is read at
+        // (H & -(GS TREE)) + 63 SZ, an address computed from the search so that
+        // the read stays with it (a constant LDS address would be hoisted out
+        // of the cell loop into a register per slot)
+        const T last = *reinterpret_cast<const T*>(ebt + j * TREE + (H[j] & -(GS * TREE)) + 63 * SZ);
+        int k = static_cast<int>(static_cast<uint32_t>(H[j] - G) / SZ) - (kSortWidth - 1);
+        k += static_cast<int>(k == kSortWidth - 1) & static_cast<int>(last <= dv[j]);
+        const unsigned char* row =
+            reinterpret_cast<const unsigned char*>(P + (TB * kNrMax + g * GS + j) * kMaskPitch);
+        cur[j] = *reinterpret_cast<const uint64_t*>(row + static_cast<uint32_t>(k) * 8u);
+      }
+    };
     uint64_t cur[GS];
+    search(std::integral_constant<int, 0>{}, cur);
+    if constexpr (TWO) {
+      // walkers whose interval of a slot ends below delta_R are not flagged by it
+      uint64_t cuh[GS];
+      search(std::integral_constant<int, 1>{}, cuh);
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-      // h = 64 + k, k in [0, 63], so H - G = SZ (63 + k) < GS TREE and G is a
-      // multiple of GS TREE: S_63 (E[63] of the slot) is read at
-      // (H & -(GS TREE)) + 63 SZ, an address computed from the search so that
-      // the read stays with it (a constant LDS address would be hoisted out
-      // of the cell loop into a register per slot)
-      const T last = *reinterpret_cast<const T*>(eb + j * TREE + (H[j] & -(GS * TREE)) + 63 * SZ);
-      int k = static_cast<int>(static_cast<uint32_t>(H[j] - G) / SZ) - (kSortWidth - 1);
-      k += static_cast<int>(k == kSortWidth - 1) & static_cast<int>(last <= dv[j]);
-      const unsigned char* row = reinterpret_cast<const unsigned char*>(P + (g * GS + j) * kMaskPitch);
-      cur[j] = *reinterpret_cast<const uint64_t*>(row + static_cast<uint32_t>(k) * 8u);
-    }
+      for (int j = 0; j < GS; ++j) {
+        acc |= pend[j] & ~pendh[j];
+        pend[j] = cur[j];
+        pendh[j] = cuh[j];
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-      acc |= pend[j];
-      pend[j] = cur[j];
+      for (int j = 0; j < GS; ++j) {
+        acc |= pend[j];
+        pend[j] = cur[j];
+      }
     }
   }
 #pragma unroll
-  for (int j = 0; j < GS; ++j) acc |= pend[j];
+  for (int j = 0; j < GS; ++j) acc |= TWO ? (pend[j] & ~pendh[j]) : pend[j];
   lo = static_cast<uint32_t>(acc);
   hi = static_cast<uint32_t>(acc >> 32);
 }
@@ -993,8 +1025,8 @@ struct IonShape {
 // that in double.
 // FIELDS: walker fw of the group also writes its x_HI and dT_b boxes (fx, fd,
 // N^3 values each) from the same per-cell values that enter its spectrum.
-// (FP32 constant-efficiency walkers with the sorted flag test take
-// k_ion_teams below instead.)
+// (FP32 walkers with the sorted flag test, constant-efficiency and
+// two-population, take k_ion_teams below instead.)
 template <typename T, typename S, int N, bool TWO, bool FIELDS>
 __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<T, N>())) void k_ion_rows(
     const S* __restrict__ dR, const T* __restrict__ odens, int nr, const WalkerConst<T>* __restrict__ wc,
@@ -1116,8 +1148,10 @@ __device__ __forceinline__ T team_sum(T v) {
   return v;
 }
 
-// Ionisation + dT_b + forward x pass for a group of constant-efficiency FP32
-// walkers with the sorted flag test, organised around the x-pass FFT teams.
+// Ionisation + dT_b + forward x pass for a group of FP32 walkers with the
+// sorted flag test, organised around the x-pass FFT teams (TWO: two-population
+// walkers, interval tables and the partial ionisation 1 - zeta_eff(t) erfc(t)
+// from the walker's cell-radius table zt).
 // Per row pair (rows 2p, 2p+1; one cell per thread) the block first finds
 // each cell's walker mask (sorted_flags) and keeps it with u = delta_c -
 // delta_cell and dT_b per unit x_HI in LDS.  Then for each batch of WB
@@ -1133,12 +1167,18 @@ __device__ __forceinline__ T team_sum(T v) {
 // non-negative terms), then the team's sum in double.  Block barriers: two
 // per row pair.  Results equal k_ion_rows' (same per-cell arithmetic and
 // transform; the x_HI sums in another order).
-template <typename S, int N, bool FIELDS>
-__global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) void k_ion_teams(
+template <int N, bool TWO>
+constexpr int team_waves_per_simd() {
+  return TWO && (N == 128 || N == 256) ? 4 : ion_waves_per_simd<float, N>();
+}
+
+template <typename S, int N, bool FIELDS, bool TWO>
+__global__ __launch_bounds__(IonShape<N>::NT, (team_waves_per_simd<N, TWO>())) void k_ion_teams(
     const S* __restrict__ dR, const float* __restrict__ odens, int nr, const WalkerConst<float>* __restrict__ wc,
     int nw, float tb, float dc, cplx<float>* __restrict__ spec, cplx<float>* __restrict__ nyq,
     double* __restrict__ xpart, const cplx<float>* __restrict__ tw, int tstride, int fw, float* __restrict__ fx,
-    float* __restrict__ fd, const float* __restrict__ Eg, const uint64_t* __restrict__ Pg) {
+    float* __restrict__ fd, const float* __restrict__ Eg, const uint64_t* __restrict__ Pg,
+    const float* __restrict__ zt) {
   using T = float;
   using IS = IonShape<N>;
   using P = FftShape<N, typename IS::Plan>;
@@ -1149,7 +1189,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
   constexpr size_t SPEC = static_cast<size_t>(N) * N * IS::HP;
   __shared__ cplx<T> lds[WB * N];
   __shared__ cplx<T> twl[N];
-  __shared__ T El[kNrMax * kSortWidth];
+  __shared__ T El[(TWO ? 2 : 1) * kNrMax * kSortWidth];
   // per cell of the row pair: walker mask halves (walkers 0..31, 32..63),
   // u = delta_c - delta_cell and dT_b per unit x_HI at half scale, tb / 2
   // times (1 + delta) times the velocity factor
@@ -1159,7 +1199,10 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
   const int t = threadIdx.x;
   const int row = t / N, x = t % N;   // the cell of the mask phase
   const int q = t / TS, j = t % TS;   // the team and member of the walker phase
-  for (int e = t; e < (nr + 3) / 4 * 4 * kSortWidth; e += NT) El[e] = Eg[e];
+  for (int e = t; e < (nr + 3) / 4 * 4 * kSortWidth; e += NT) {
+    El[e] = Eg[e];
+    if constexpr (TWO) El[kNrMax * kSortWidth + e] = Eg[kNrMax * kSortWidth + e];
+  }
   for (int w = t; w < kMaxGroup; w += NT) acc[w] = 0.0;
   load_twiddles<N>(twl, tw, tstride);
   const T tbh = T(0.5) * tb;   // dT_b at half scale: the unpacking needs no halving
@@ -1200,6 +1243,15 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
         if constexpr (PARTIAL == 2) {
           xh = T(0);
           if (!(cm[e] & bit)) xh = partial_xhi_pos(cw, u, u * u);
+        } else if constexpr (TWO) {
+          // the two-population form: 1 - zeta_eff(t) erfc(t), t = max(a u, 0)
+          xh = T(1);
+          if (cm[e] & bit) {
+            xh = T(0);
+          } else if (cw.partial) {
+            const T tt = max(cw.a_cell * u, T(0));
+            xh = T(1) - zeta_eff(zt + static_cast<size_t>(w) * kZetaPitch, tt) * erfc_t(tt);
+          }
         } else {
           xh = T(1);
           if (cm[e] & bit)
@@ -1230,7 +1282,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
     {
       const size_t cell = static_cast<size_t>(2 * p + row) * N + x;
       uint32_t mlo = 0, mhi = 0;
-      sorted_flags<T, S>(dR, N3, cell, nr, El, Pg, mlo, mhi);
+      sorted_flags<T, S, TWO>(dR, N3, cell, nr, El, Pg, mlo, mhi);
       const T d0 = load_as<T>(dR, static_cast<size_t>(nr - 1) * N3 + cell);
       cmask[0][t] = mlo;
       cmask[1][t] = mhi;
@@ -1262,7 +1314,7 @@ __global__ __launch_bounds__(IonShape<N>::NT, (ion_waves_per_simd<float, N>())) 
       bool all2 = true;
 #pragma unroll
       for (int i = 0; i < TPW; ++i) all2 = all2 && cw[i].partial == 2;
-      if (all2)
+      if (!TWO && all2)
         cells(std::integral_constant<int, 2>{}, c, cm, bit, live, w, p, v, xs);
       else
         cells(std::integral_constant<int, -1>{}, c, cm, bit, live, w, p, v, xs);
@@ -1759,8 +1811,9 @@ bool ion_sorted_default() {
 }
 
 size_t slot_table_bytes() {
+  // E: two FP32 sets in the space of one FP64 set; P: two sets
   return static_cast<size_t>(kNrMax) * kSortWidth * sizeof(double) +
-         static_cast<size_t>(kNrMax) * kMaskPitch * sizeof(uint64_t);
+         2 * static_cast<size_t>(kNrMax) * kMaskPitch * sizeof(uint64_t);
 }
 
 hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void* odens, int nr, const void* wc,
@@ -1771,7 +1824,7 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
   const bool fields = field_walker >= 0;
   if (fields && (field_walker >= nw || !x_hi || !dtb)) return hipErrorInvalidValue;
   const bool want_sorted = flag_test < 0 ? ion_sorted_default() : flag_test == 1;
-  const bool sorted = slot_tab && !zt && dtype == kF32 && want_sorted;
+  const bool sorted = slot_tab && dtype == kF32 && want_sorted;
   return with_real(dtype, [&](auto tv) {
     using T = decltype(tv);
     return with_storage<T>(storage, [&](auto sv) {
@@ -1791,26 +1844,30 @@ hipError_t launch_ion(int dtype, int storage, int n, const void* dR, const void*
                              static_cast<T*>(dtb));
           return hipGetLastError();
         };
-        if (zt) return fields ? go(std::true_type{}, std::true_type{}) : go(std::true_type{}, std::false_type{});
         if (sorted) {   // FP32 only (see `sorted` above)
-          hipLaunchKernelGGL((k_slot_tables<T>), dim3(static_cast<unsigned>(kNrMax)), dim3(kSortWidth), 0, s,
-                             static_cast<const T*>(thr), nw, E, P);
+          const int sets = zt ? 2 : 1;   // two-population walkers: intervals
+          hipLaunchKernelGGL((k_slot_tables<T>), dim3(static_cast<unsigned>(sets * kNrMax)), dim3(kSortWidth), 0, s,
+                             static_cast<const T*>(thr), sets * kNrMax, nw, E, P);
           hipError_t e = hipGetLastError();
           if (e != hipSuccess) return e;
           if constexpr (std::is_same<T, float>::value) {
-            const auto teams = [&](auto withf) {
-              hipLaunchKernelGGL((k_ion_teams<ST, N, decltype(withf)::value>), dim3(ion_grid(N, blocks)),
+            const auto teams = [&](auto withf, auto two) {
+              hipLaunchKernelGGL((k_ion_teams<ST, N, decltype(withf)::value, decltype(two)::value>),
+                                 dim3(ion_grid(N, blocks)),
                                  dim3(IonShape<N>::NT), 0, s, static_cast<const ST*>(dR),
                                  static_cast<const T*>(odens), nr, static_cast<const WalkerConst<T>*>(wc), nw,
                                  static_cast<T>(tb), static_cast<T>(dc), static_cast<cplx<T>*>(spec),
                                  static_cast<cplx<T>*>(nyq), xpart, static_cast<const cplx<T>*>(tw), ntab / N,
                                  field_walker, static_cast<T*>(x_hi), static_cast<T*>(dtb),
-                                 static_cast<const T*>(E), static_cast<const uint64_t*>(P));
+                                 static_cast<const T*>(E), static_cast<const uint64_t*>(P),
+                                 static_cast<const T*>(zt));
               return hipGetLastError();
             };
-            return fields ? teams(std::true_type{}) : teams(std::false_type{});
+            if (zt) return fields ? teams(std::true_type{}, std::true_type{}) : teams(std::false_type{}, std::true_type{});
+            return fields ? teams(std::true_type{}, std::false_type{}) : teams(std::false_type{}, std::false_type{});
           }
         }
+        if (zt) return fields ? go(std::true_type{}, std::true_type{}) : go(std::true_type{}, std::false_type{});
         return fields ? go(std::false_type{}, std::true_type{}) : go(std::false_type{}, std::false_type{});
       });
     });

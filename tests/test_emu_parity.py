@@ -269,6 +269,31 @@ def test_emu_two_population():
             assert np.abs(x - ev.x_hi)[same].max() <= 2e-7
 
 
+def test_emu_two_population_f32():
+    """FP32 two-population walkers take the sorted interval test of the team
+    ionisation pass (two searches per slot: lower ends, raised upper ends);
+    P(k) and the mean x_HI against the oracle, FP32 bounds."""
+    specs = [(16, 12.0, 8.0, 4)]
+    walkers = EDGE2[:5] + EDGE2[6:]
+    run = eh.EmuRun(storage="f32", max_walkers=4, phys={"pk_amp": AMP})
+    n, box, z, nb = specs[0]
+    d = synth.make_box(n, box, z, seed=80, amp=AMP, dtype=np.float32)
+    run.box(d, box, z, nb)
+    for w in walkers:
+        run.walker2(*w)
+    run.cmd("prepare")
+    run.cmd(f"batch2 {nb}")
+    run.run()
+    pk = run.read("batch2_pk.bin", np.float64, (len(walkers), 1, nb))
+    xm = run.read("batch2_xhi.bin", np.float64, (len(walkers), 1))
+    shared = oracle.shared_radii(n, box, PHYS)
+    for wi, w in enumerate(walkers):
+        ev = oracle.two_population.evaluate(d, box, z, w, oracle.walker_radii(shared, w[1]), nb, PHYS)
+        ok = ev.counts > 0
+        np.testing.assert_allclose(pk[wi, 0][ok], ev.pk[ok], rtol=1e-3, atol=1e-3 * ev.pk[ok].max())
+        assert xm[wi, 0] == pytest.approx(ev.xhi_mean, abs=1e-4)
+
+
 def _oracle_chain(boxes, specs, mocks, dim, lo, hi, x0, u, a=2.0):
     """The oracle sampler's chain with ln p = -chi^2 / 2 from full oracle evaluations."""
     def loglike(p):

@@ -649,6 +649,30 @@ def test_two_population_vs_oracle(xs, dtype):
     ctx.close()
 
 
+def test_two_population_sorted_equals_per_walker(xs):
+    """FP32 two-population walkers: the sorted interval test of the team ionisation pass
+    (lower ends, and upper ends raised to the next float, two searches per radius slot;
+    flag_test 1) flags exactly the cells the per-walker compares flag (flag_test 0):
+    the mean x_HI agrees to summation order (one flipped cell of 64^3 would move it by
+    3.8e-6) and P(k) to FP32 rounding, for every edge walker, bounded intervals included."""
+    n, box, z, nb = 64, 32.0, 8.0, 8
+    d = synth.make_box(n, box, z, seed=91, amp=AMP, dtype=np.float32)
+    ctx = _ctx(xs)
+    b = ctx.add_box(d, box, z, nb)
+    ctx.prepare("f32", max_walkers=8, max_plain_radii=30)
+    ctx.set_tuning(n, flag_test=1)
+    pk1, x1 = ctx.eval_batch2([b], EDGE2)
+    ctx.set_tuning(n, flag_test=0)
+    pk0, x0 = ctx.eval_batch2([b], EDGE2)
+    ctx.set_tuning(n)
+    pk1, x1, pk0, x0 = (t.cpu().numpy() for t in (pk1, x1, pk0, x0))
+    print(f"[two-pop sorted vs per-walker] max |dx_HI mean| = {np.abs(x1 - x0).max():.2e}, "
+          f"max P(k) rel = {np.max(np.abs(pk1 - pk0) / np.maximum(np.abs(pk0), 1e-30)):.2e}", flush=True)
+    np.testing.assert_allclose(x1, x0, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(pk1, pk0, rtol=1e-5, atol=1e-5 * np.abs(pk0).max())
+    ctx.close()
+
+
 def test_two_population_256_sampled(xs):
     """The benchmark geometry (256^3 x 3 z, 64 walkers per launch) with drawn two-population
     walkers: flags and x_HI of sampled cells against the oracle cell by cell, and the
