@@ -269,13 +269,20 @@ def test_emu_two_population():
             assert np.abs(x - ev.x_hi)[same].max() <= 2e-7
 
 
+# Two-population walkers with narrow flag intervals: on the 16^3, 32 Mpc box
+# below, 3 and 6 cells skip over the interval between radii, so that only the
+# upper ends keep them unflagged (by the oracle's per-radius fractions).
+NARROW2 = [(15.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0), (20.0, 15.0, 3e5, 10.0 / 3.0, -10.0 / 3.0)]
+
+
 def test_emu_two_population_f32():
     """FP32 two-population walkers take the sorted interval test of the team
     ionisation pass (two searches per slot: lower ends, raised upper ends);
-    P(k) and the mean x_HI against the oracle, FP32 bounds."""
-    specs = [(16, 12.0, 8.0, 4)]
-    walkers = EDGE2[:5] + EDGE2[6:]
-    run = eh.EmuRun(storage="f32", max_walkers=4, phys={"pk_amp": AMP})
+    P(k) and the mean x_HI against the oracle, FP32 bounds (one cell of 16^3
+    moves the mean by 2.4e-4), walkers whose upper ends decide cells included."""
+    specs = [(16, 32.0, 8.5, 4)]
+    walkers = EDGE2[:5] + EDGE2[6:] + NARROW2
+    run = eh.EmuRun(storage="f32", max_walkers=8, phys={"pk_amp": AMP})
     n, box, z, nb = specs[0]
     d = synth.make_box(n, box, z, seed=80, amp=AMP, dtype=np.float32)
     run.box(d, box, z, nb)

@@ -649,27 +649,45 @@ def test_two_population_vs_oracle(xs, dtype):
     ctx.close()
 
 
+# Walkers whose flag intervals are narrow enough that some cells of the 32^3
+# box below skip over them between radii: at those cells only the upper ends
+# of the intervals keep the cell unflagged (at least 181 and 263 cells by the
+# oracle's per-radius fractions).
+NARROW2 = [(15.0, 15.0, 1e5, 10.0 / 3.0, -4.0 / 3.0), (20.0, 15.0, 3e5, 10.0 / 3.0, -10.0 / 3.0)]
+
+
 def test_two_population_sorted_equals_per_walker(xs):
     """FP32 two-population walkers: the sorted interval test of the team ionisation pass
     (lower ends, and upper ends raised to the next float, two searches per radius slot;
     flag_test 1) flags exactly the cells the per-walker compares flag (flag_test 0):
-    the mean x_HI agrees to summation order (one flipped cell of 64^3 would move it by
-    3.8e-6) and P(k) to FP32 rounding, for every edge walker, bounded intervals included."""
-    n, box, z, nb = 64, 32.0, 8.0, 8
-    d = synth.make_box(n, box, z, seed=91, amp=AMP, dtype=np.float32)
+    the mean x_HI agrees to summation order (one flipped cell of 32^3 would move it by
+    3e-5) and P(k) to FP32 rounding, for every edge walker and two walkers whose upper
+    interval ends decide cells; those two also against the oracle."""
+    n, box, z, nb = 32, 64.0, 8.5, 6
+    d = synth.make_box(n, box, z, seed=43, amp=AMP, dtype=np.float32)
+    walkers = EDGE2 + NARROW2
     ctx = _ctx(xs)
     b = ctx.add_box(d, box, z, nb)
-    ctx.prepare("f32", max_walkers=8, max_plain_radii=30)
+    ctx.prepare("f32", max_walkers=len(walkers), max_plain_radii=30)
     ctx.set_tuning(n, flag_test=1)
-    pk1, x1 = ctx.eval_batch2([b], EDGE2)
+    pk1, x1 = ctx.eval_batch2([b], walkers)
     ctx.set_tuning(n, flag_test=0)
-    pk0, x0 = ctx.eval_batch2([b], EDGE2)
+    pk0, x0 = ctx.eval_batch2([b], walkers)
     ctx.set_tuning(n)
     pk1, x1, pk0, x0 = (t.cpu().numpy() for t in (pk1, x1, pk0, x0))
     print(f"[two-pop sorted vs per-walker] max |dx_HI mean| = {np.abs(x1 - x0).max():.2e}, "
           f"max P(k) rel = {np.max(np.abs(pk1 - pk0) / np.maximum(np.abs(pk0), 1e-30)):.2e}", flush=True)
     np.testing.assert_allclose(x1, x0, rtol=0, atol=1e-7)
     np.testing.assert_allclose(pk1, pk0, rtol=1e-5, atol=1e-5 * np.abs(pk0).max())
+    shared = ctx.radii(b)
+    for i, w in enumerate(NARROW2):
+        wi = len(EDGE2) + i
+        ev = oracle.two_population.evaluate(d.astype(np.float64), box, z, w, oracle.walker_radii(shared, w[1]),
+                                            nb, PHYS)
+        x, _ = ctx.materialize2(b, w)
+        flips, rel = report(f"two-pop-narrow w{i}", x.cpu().numpy(), ev, pk1[wi, 0], x1[wi, 0])
+        assert flips <= 1e-4 and rel <= 1e-3
+        assert abs(x1[wi, 0] - ev.xhi_mean) <= 1e-4
     ctx.close()
 
 
